@@ -1,0 +1,260 @@
+/*
+ * vip.h -- C ABI of libvip, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of variational full-waveform inversion with SVGD and
+ * stochastic SVGD (Zhang & Curtis, "VIP - Variational Inversion Package",
+ * arXiv 2310.13325).
+ *
+ * The inversion layer needs, per particle, the log-posterior value and its
+ * gradient (section 3, "Code overview"); the particles are then moved by the
+ * SVGD update (eq:phi_mean) or the stochastic SVGD update
+ * (eq:stochastic_svgd with the noise of eq:noise_term).  The four calls of
+ * that contract are vip_forward, vip_grad_logpost, vip_svgd_step and
+ * vip_ssvgd_step; the rest supports them (workspace sizing, tapes for
+ * reverse-mode differentiation, batching of several problems, status).
+ *
+ * Conventions (all calls):
+ *  - Units SI (m, s, m/s).  Arrays row-major; a velocity model is [nz][nx]
+ *    with x (columns) fastest; a particle ensemble X is [n][d], d = nz*nx,
+ *    i.e. the velocity models stacked.
+ *  - Pointers marked "device" are HIP device (or managed) memory on the
+ *    context's device; "host" pointers are read during the call only.
+ *  - Ownership: the caller owns every buffer.  The library never allocates or
+ *    frees device memory in a call; scratch comes from a caller workspace
+ *    whose size the matching *_workspace query returns.  Workspaces must be
+ *    256-byte aligned.
+ *  - Execution: work is enqueued asynchronously on the context stream; no call
+ *    synchronises except vip_poll and vip_destroy.  Results are bitwise
+ *    reproducible for identical inputs (no floating-point atomics).
+ *  - Errors: the return value reports host-side validation (shapes, indices,
+ *    stability limit, workspace size) and launch failures; nothing is enqueued
+ *    when validation fails.  Conditions found on the device (non-finite
+ *    values, a velocity above the declared bound, a Cholesky factorisation
+ *    that fails after its jitter retries) are latched in a status word inside
+ *    the workspace and read with vip_poll.
+ *  - One host thread per context.
+ */
+#ifndef VIP_H
+#define VIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VIP_OK = 0,
+  VIP_E_ARG = -1,         /* bad shape, null pointer, index outside the grid */
+  VIP_E_CFL = -2,         /* vmax*dt*sqrt(4/3 (1/dx^2 + 1/dz^2)) > 1 */
+  VIP_E_WORKSPACE = -3,   /* workspace too small or misaligned */
+  VIP_E_HIP = -4,         /* HIP runtime error (launch, capture, device) */
+  VIP_E_NOT_PD = -5,      /* kernel matrix not positive definite after jitter */
+  VIP_E_NONFINITE = -6,   /* NaN / Inf met on the device */
+  VIP_E_UNSUPPORTED = -7  /* option not implemented */
+} vip_status;
+
+/* Device status bits latched in a workspace and returned by vip_poll. */
+#define VIP_FLAG_NONFINITE   0x1u  /* NaN/Inf in velocity, data, misfit or update */
+#define VIP_FLAG_VMAX        0x2u  /* a velocity <= 0 or above vip_grid.vmax */
+#define VIP_FLAG_NOT_PD      0x4u  /* Cholesky failed after all jitter retries */
+#define VIP_FLAG_JITTER      0x8u  /* Cholesky needed at least one jitter retry */
+
+typedef struct vip_ctx vip_ctx;
+
+/* Finite-difference grid.  The model has nz x nx cells of size dz x dx; the
+ * simulation grid adds an absorbing sponge of nb cells on every side
+ * (NZ = nz + 2 nb, NX = nx + 2 nb) whose velocity replicates the model's edge
+ * cells.  Time samples t_n = n dt, n = 0 .. nt-1.  The scheme is second order
+ * in time and fourth order in space for (1/v^2) u_tt - lap u = f, damped by
+ * the Cerjan factor g = exp(-(alpha delta_z)^2) exp(-(alpha delta_x)^2),
+ * delta = distance into the sponge in cells (the paper's FD method, section
+ * 4.2, leaves order and boundary open; these are the readings taken).
+ * vmax is an upper bound of every velocity the call may see (e.g. the prior's
+ * upper bound); it is checked against the stability limit on the host and
+ * against the actual velocities on the device. */
+typedef struct {
+  int32_t nx, nz, nb, nt;
+  double dx, dz, dt;
+  double sponge_alpha;
+  double vmax;
+} vip_grid;
+
+/* Acquisition (section 4.2): ns shots, one point source each, recorded by the
+ * same nr receivers.  Indices are interior cell indices (0 <= ix < nx,
+ * 0 <= iz < nz), host arrays.  wavelet is the source time function w(t_n),
+ * device float [nt]; the source term is w(t_n)/(dx dz) at the shot node
+ * (vip_ricker fills a Ricker wavelet). */
+typedef struct {
+  int32_t ns;
+  const int32_t *src_ix, *src_iz;
+  int32_t nr;
+  const int32_t *rec_ix, *rec_iz;
+  const float *wavelet;
+} vip_geometry;
+
+/* Prior (section 3): VIP_PRIOR_NONE, or a uniform prior on [lo, hi] per
+ * coordinate applied by strategy 1 -- after an update, values outside the
+ * bounds are reset to the nearest bound.  lo, hi: device float [d].  With the
+ * uniform prior the log-prior is 0 inside the bounds (normalisation dropped)
+ * and its gradient is 0. */
+#define VIP_PRIOR_NONE 0
+#define VIP_PRIOR_UNIFORM_CLIP 1
+typedef struct {
+  int32_t kind;
+  const float *lo, *hi;
+} vip_prior;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a
+ * hipStream_t; NULL = the legacy default stream).  Allocates host-side state
+ * and one internal stream used for graph replay; no device memory. */
+vip_status vip_create(vip_ctx **ctx, int device, void *stream);
+/* Synchronise and release the context (and any cached graphs). */
+vip_status vip_destroy(vip_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+vip_status vip_set_stream(vip_ctx *ctx, void *stream);
+/* Graph mode: when on, vip_grad_logpost / vip_forward capture their whole
+ * launch sequence into a hipGraph the first time they see a given argument
+ * set and replay it afterwards (the arguments, including pointers, form the
+ * cache key).  Off by default. */
+vip_status vip_set_graph_mode(vip_ctx *ctx, int enable);
+/* Human-readable name of a status code (static string). */
+const char *vip_status_string(int status);
+/* Library version, major*10000 + minor*100 + patch. */
+int vip_version(void);
+
+/* Synchronise the context stream, then read and clear the device status word
+ * of a workspace previously passed to a call.  *flags gets VIP_FLAG_* bits. */
+vip_status vip_poll(vip_ctx *ctx, void *ws, uint32_t *flags);
+
+/* Fill out[n] = (1 - 2 a) exp(-a), a = (pi f0 (n dt - t0))^2, n < nt: the
+ * unit-peak Ricker wavelet of section 4.2 (t0 <= 0 selects t0 = 1.5/f0).
+ * out: device float [nt]. */
+vip_status vip_ricker(vip_ctx *ctx, int32_t nt, double dt, double f0, double t0, float *out);
+
+/* ---- forward modelling ------------------------------------------------- */
+
+/* Workspace bytes for vip_forward with np particles. */
+vip_status vip_forward_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                                 size_t *bytes);
+
+/* Simulate every (particle, shot) pair: data[p][s][n][r] = u_{p,s}^n(x_r),
+ * n = 0 .. nt-1 (u^0 = 0), for the velocity models vel (device float
+ * [np][nz][nx]).  data: device float [np][ns][nt][nr]. */
+vip_status vip_forward(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                       const float *vel, float *data, void *ws, size_t ws_bytes);
+
+/* ---- log-posterior and its gradient ------------------------------------ */
+
+/* Workspace bytes for vip_grad_logpost.  ckpt_every = k: the forward state is
+ * stored every k steps and each k-step segment is recomputed once during the
+ * adjoint sweep (k >= nt-1 keeps one segment: the whole history).
+ * live_pairs: how many (particle, shot) pairs are simulated at once
+ * (0 = all np*ns); memory grows linearly with it. */
+vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                                      int32_t ckpt_every, int32_t live_pairs, size_t *bytes);
+
+/* For every particle p (vel[p], device float [np][nz][nx]):
+ *   logpost[p] = -J_p + log prior,  J_p = 1/2 sum_{s,n,r} (d_{p,s,n,r} - dobs_{s,n,r})^2 / sigma^2
+ * (eq:likelihood with one standard deviation sigma for all samples, constants
+ * dropped), and grad[p] = d logpost / d vel[p], obtained by the adjoint-state
+ * method (section 3) on the exact discrete adjoint of the forward scheme:
+ * forward sweep with checkpoints, then per segment a recompute sweep and an
+ * adjoint sweep with the imaging sum accumulated in FP64 across segments and
+ * shots.
+ * dobs: device float [ns][nt][nr].  logpost: device double [np].
+ * grad: device float [np][nz][nx].  prior may be NULL (no prior). */
+vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                            const vip_prior *prior, int32_t np, const float *vel,
+                            const float *dobs, double sigma, int32_t ckpt_every, int32_t live_pairs,
+                            double *logpost, float *grad, void *ws, size_t ws_bytes);
+
+/* Same result through the plain per-pair path: one pair at a time, one launch
+ * per time step and per fused-away operation, global-memory stencil.  It exists
+ * as the baseline that the batched path is measured against. */
+vip_status vip_grad_logpost_plain_workspace(const vip_grid *grid, const vip_geometry *geom,
+                                            int32_t np, size_t *bytes);
+vip_status vip_grad_logpost_plain(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                                  const vip_prior *prior, int32_t np, const float *vel,
+                                  const float *dobs, double sigma, double *logpost, float *grad,
+                                  void *ws, size_t ws_bytes);
+
+/* ---- tapes: reverse-mode differentiation of vip_forward ----------------- */
+
+/* Tape bytes: the checkpointed forward states of all np*ns pairs. */
+vip_status vip_tape_bytes(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                          int32_t ckpt_every, size_t *bytes);
+/* Workspace bytes shared by vip_forward_tape and vip_adjoint_tape. */
+vip_status vip_tape_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                              int32_t ckpt_every, size_t *bytes);
+/* vip_forward that also records the checkpoints in `tape` (device). */
+vip_status vip_forward_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                            int32_t np, const float *vel, float *data, int32_t ckpt_every,
+                            void *tape, size_t tape_bytes, void *ws, size_t ws_bytes);
+/* Vector-Jacobian product of vip_forward at vel: grad_vel[p] =
+ * sum_{s,n,r} grad_data[p][s][n][r] d data[p][s][n][r] / d vel[p], from the
+ * tape written by vip_forward_tape with the same vel and ckpt_every.
+ * grad_data: device float [np][ns][nt][nr]; grad_vel: device float
+ * [np][nz][nx] (overwritten). */
+vip_status vip_adjoint_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                            int32_t np, const float *vel, int32_t ckpt_every, const void *tape,
+                            size_t tape_bytes, const float *grad_data, float *grad_vel, void *ws,
+                            size_t ws_bytes);
+
+/* ---- SVGD / sSVGD ------------------------------------------------------- */
+
+#define VIP_BW_MEDIAN_ALL 0      /* median of all n^2 squared distances (zeros included) */
+#define VIP_BW_MEDIAN_OFFDIAG 1  /* median of the n(n-1)/2 distinct pairs */
+#define VIP_BW_FIXED 2           /* h = h_fixed */
+#define VIP_GRAM_BF16 0          /* X_c X_c^T on BF16 matrix cores, FP32 accumulation */
+#define VIP_GRAM_FP32 1          /* X_c X_c^T in FP32 on the vector units */
+
+/* Workspace bytes for vip_svgd_step / vip_ssvgd_step with n particles of
+ * dimension d. */
+vip_status vip_svgd_workspace(int32_t n, int64_t d, size_t *bytes);
+
+/* Offsets (bytes from the workspace start) of intermediate results that stay
+ * valid in the workspace after a step, for inspection:
+ * D float [n][n] squared distances, K float [n][n] kernel matrix,
+ * h2 double [1] bandwidth h^2, L double [n][n] Cholesky factor of K/n (sSVGD),
+ * phi float [n][d] the SVGD direction. */
+typedef struct {
+  size_t D, K, h2, L, phi;
+} vip_svgd_layout;
+vip_status vip_svgd_layout_of(int32_t n, int64_t d, vip_svgd_layout *out);
+
+/* One SVGD iteration (eq:rbf, eq:phi_mean) on x (device float [n][d], updated
+ * in place) with gradients g = grad log p(x_i) (device float [n][d]):
+ *   D_ij = |x_i - x_j|^2;  h^2 = med / (2 ln(n+1)) (h^2 = 1 if med = 0), or h_fixed^2;
+ *   K_ij = exp(-D_ij / (2 h^2));  s_i = sum_j K_ij;
+ *   phi_i = 1/n [ sum_j K_ij g_j + (s_i x_i - sum_j K_ij x_j) / h^2 ];
+ *   x_i <- clip(x_i + eps phi_i) (clip only with a uniform prior).
+ * Distances come from the Gram matrix of the centred particles, on BF16 matrix
+ * cores or in FP32 (gram_prec).  h2_out: device double [1] or NULL. */
+vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
+                         int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                         const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes);
+
+/* One stochastic SVGD iteration (eq:stochastic_svgd): the SVGD direction plus
+ * noise eta = sqrt(2 eps) L xi per coordinate, L the lower Cholesky factor of
+ * K/n (eq:matrixDK, eq:noise_term; factorised in FP64 on the device, with
+ * jitter 1e-12 trace/n x10 per retry, at most 6 retries), then the prior clip.
+ * xi: device float [n][d] standard normals, or NULL to draw them with
+ * Philox4x32-10 (key = seed, counter = (element/4, stream)) and Box-Muller. */
+vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
+                          int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                          const vip_prior *prior, const float *xi, uint64_t seed, uint64_t stream,
+                          double *h2_out, void *ws, size_t ws_bytes);
+
+/* Standard normals out[e], e < count, from Philox4x32-10 as described for
+ * vip_ssvgd_step (device float [count]). */
+vip_status vip_philox_normals(vip_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream,
+                              float *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIP_H */

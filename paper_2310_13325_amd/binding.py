@@ -1,0 +1,440 @@
+"""ctypes binding of libvip (include/vip.h) over torch device tensors.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libvip.so.  torch provides device memory (inputs, outputs and the
+workspaces the library asks for) and the stream the library enqueues on.
+There is no fallback: a missing library or a call on a machine without a GPU
+raises.
+
+The call names follow the C ABI: vip_forward, vip_grad_logpost,
+vip_svgd_step, vip_ssvgd_step (plus the tape, plain-path and batching calls).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvip.so")
+
+VIP_OK = 0
+VIP_PRIOR_NONE = 0
+VIP_PRIOR_UNIFORM_CLIP = 1
+VIP_BW_MEDIAN_ALL = 0
+VIP_BW_MEDIAN_OFFDIAG = 1
+VIP_BW_FIXED = 2
+VIP_GRAM_BF16 = 0
+VIP_GRAM_FP32 = 1
+VIP_FLAG_NONFINITE = 0x1
+VIP_FLAG_VMAX = 0x2
+VIP_FLAG_NOT_PD = 0x4
+VIP_FLAG_JITTER = 0x8
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+class VipGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("dx", ctypes.c_double), ("dz", ctypes.c_double),
+                ("dt", ctypes.c_double), ("sponge_alpha", ctypes.c_double),
+                ("vmax", ctypes.c_double)]
+
+
+class VipGeometry(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int32), ("src_ix", _i32p), ("src_iz", _i32p),
+                ("nr", ctypes.c_int32), ("rec_ix", _i32p), ("rec_iz", _i32p),
+                ("wavelet", ctypes.c_void_p)]
+
+
+class VipPrior(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p)]
+
+
+class VipSvgdLayout(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_size_t), ("K", ctypes.c_size_t), ("h2", ctypes.c_size_t),
+                ("L", ctypes.c_size_t), ("phi", ctypes.c_size_t)]
+
+
+class VipError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2310_13325_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.c_uint64, ctypes.c_double)
+        G, GE, PR = ctypes.POINTER(VipGrid), ctypes.POINTER(VipGeometry), ctypes.POINTER(VipPrior)
+        szp = ctypes.POINTER(sz)
+        sig = {
+            "vip_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "vip_version": (ctypes.c_int, []),
+            "vip_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp]),
+            "vip_destroy": (ctypes.c_int, [vp]),
+            "vip_set_stream": (ctypes.c_int, [vp, vp]),
+            "vip_set_graph_mode": (ctypes.c_int, [vp, ctypes.c_int]),
+            "vip_poll": (ctypes.c_int, [vp, vp, ctypes.POINTER(ctypes.c_uint32)]),
+            "vip_ricker": (ctypes.c_int, [vp, i32, dbl, dbl, dbl, vp]),
+            "vip_forward_workspace": (ctypes.c_int, [G, GE, i32, szp]),
+            "vip_forward": (ctypes.c_int, [vp, G, GE, i32, vp, vp, vp, sz]),
+            "vip_grad_logpost_workspace": (ctypes.c_int, [G, GE, i32, i32, i32, szp]),
+            "vip_grad_logpost": (ctypes.c_int, [vp, G, GE, PR, i32, vp, vp, dbl, i32, i32, vp, vp,
+                                                vp, sz]),
+            "vip_grad_logpost_plain_workspace": (ctypes.c_int, [G, GE, i32, szp]),
+            "vip_grad_logpost_plain": (ctypes.c_int, [vp, G, GE, PR, i32, vp, vp, dbl, vp, vp, vp,
+                                                      sz]),
+            "vip_tape_bytes": (ctypes.c_int, [G, GE, i32, i32, szp]),
+            "vip_tape_workspace": (ctypes.c_int, [G, GE, i32, i32, szp]),
+            "vip_forward_tape": (ctypes.c_int, [vp, G, GE, i32, vp, vp, i32, vp, sz, vp, sz]),
+            "vip_adjoint_tape": (ctypes.c_int, [vp, G, GE, i32, vp, i32, vp, sz, vp, vp, vp, sz]),
+            "vip_svgd_workspace": (ctypes.c_int, [i32, i64, szp]),
+            "vip_svgd_layout_of": (ctypes.c_int, [i32, i64, ctypes.POINTER(VipSvgdLayout)]),
+            "vip_svgd_step": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR, vp, vp,
+                                             sz]),
+            "vip_ssvgd_step": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR, vp,
+                                              u64, u64, vp, vp, sz]),
+            "vip_philox_normals": (ctypes.c_int, [vp, i64, u64, u64, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    try:
+        return lib().vip_status_string(int(s)).decode()
+    except Exception:
+        return "unknown"
+
+
+def _check(status: int, where: str):
+    if status != VIP_OK:
+        raise VipError(status, where)
+
+
+# ----------------------------------------------------------------------------
+# Plain-python descriptions of a problem, converted to the C structs per call
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Grid:
+    nx: int
+    nz: int
+    nt: int
+    dx: float
+    dt: float
+    vmax: float
+    nb: int = 20
+    dz: Optional[float] = None
+    sponge_alpha: float = 0.015
+
+    def c(self) -> VipGrid:
+        return VipGrid(self.nx, self.nz, self.nb, self.nt, self.dx,
+                       self.dx if self.dz is None else self.dz, self.dt, self.sponge_alpha,
+                       self.vmax)
+
+
+class Geometry:
+    """Shot / receiver interior indices (host) and the device wavelet."""
+
+    def __init__(self, src_iz: Sequence[int], src_ix: Sequence[int], rec_iz: Sequence[int],
+                 rec_ix: Sequence[int], wavelet: torch.Tensor):
+        self.src_iz = np.ascontiguousarray(src_iz, dtype=np.int32)
+        self.src_ix = np.ascontiguousarray(src_ix, dtype=np.int32)
+        self.rec_iz = np.ascontiguousarray(rec_iz, dtype=np.int32)
+        self.rec_ix = np.ascontiguousarray(rec_ix, dtype=np.int32)
+        assert len(self.src_iz) == len(self.src_ix) and len(self.rec_iz) == len(self.rec_ix)
+        self.wavelet = wavelet
+
+    @property
+    def ns(self):
+        return len(self.src_iz)
+
+    @property
+    def nr(self):
+        return len(self.rec_iz)
+
+    def c(self) -> VipGeometry:
+        p = lambda a: a.ctypes.data_as(_i32p)
+        w = self.wavelet.data_ptr() if self.wavelet is not None else None
+        return VipGeometry(self.ns, p(self.src_ix), p(self.src_iz), self.nr, p(self.rec_ix),
+                           p(self.rec_iz), w)
+
+
+def _prior(lo: Optional[torch.Tensor], hi: Optional[torch.Tensor]):
+    if lo is None:
+        return None
+    return VipPrior(VIP_PRIOR_UNIFORM_CLIP, _ptr(lo, torch.float32), _ptr(hi, torch.float32))
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+class Context:
+    """A libvip context on one device; enqueues on torch's current stream."""
+
+    def __init__(self, device: int = 0, graph_mode: bool = False):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libvip needs a HIP device; none is visible")
+        self.device = torch.device("cuda", device)
+        self._h = ctypes.c_void_p()
+        _check(lib().vip_create(ctypes.byref(self._h), device,
+                                ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)),
+               "vip_create")
+        if graph_mode:
+            _check(lib().vip_set_graph_mode(self._h, 1), "vip_set_graph_mode")
+        self._ws = {}
+
+    def close(self):
+        if self._h:
+            lib().vip_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sync_stream(self):
+        _check(lib().vip_set_stream(
+            self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)),
+            "vip_set_stream")
+
+    def set_graph_mode(self, on: bool):
+        _check(lib().vip_set_graph_mode(self._h, 1 if on else 0), "vip_set_graph_mode")
+
+    def workspace(self, tag: str, nbytes: int) -> torch.Tensor:
+        """Zero-initialised device workspace reused across calls with the same tag."""
+        ws = self._ws.get(tag)
+        if ws is None or ws.numel() < nbytes:
+            self._ws.pop(tag, None)
+            ws = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+            self._ws[tag] = ws
+        return ws
+
+    def poll(self, ws: torch.Tensor) -> int:
+        flags = ctypes.c_uint32(0)
+        _check(lib().vip_poll(self._h, ctypes.c_void_p(ws.data_ptr()), ctypes.byref(flags)),
+               "vip_poll")
+        return int(flags.value)
+
+
+# ----------------------------------------------------------------------------
+# Calls
+# ----------------------------------------------------------------------------
+
+def vip_ricker(ctx: Context, nt: int, dt: float, f0: float, t0: float = 0.0) -> torch.Tensor:
+    ctx.sync_stream()
+    out = torch.empty(nt, dtype=torch.float32, device=ctx.device)
+    _check(lib().vip_ricker(ctx.handle, nt, dt, f0, t0, ctypes.c_void_p(out.data_ptr())),
+           "vip_ricker")
+    return out
+
+
+def vip_forward(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
+                data: Optional[torch.Tensor] = None) -> torch.Tensor:
+    ctx.sync_stream()
+    npart = vel.shape[0]
+    g, ge = grid.c(), geom.c()
+    nbytes = ctypes.c_size_t()
+    _check(lib().vip_forward_workspace(ctypes.byref(g), ctypes.byref(ge), npart,
+                                       ctypes.byref(nbytes)), "vip_forward_workspace")
+    ws = ctx.workspace("forward", nbytes.value)
+    if data is None:
+        data = torch.empty((npart, geom.ns, grid.nt, geom.nr), dtype=torch.float32,
+                           device=ctx.device)
+    _check(lib().vip_forward(ctx.handle, ctypes.byref(g), ctypes.byref(ge), npart,
+                             _ptr(vel, torch.float32), _ptr(data, torch.float32),
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel()), "vip_forward")
+    return data
+
+
+def grad_logpost_workspace_bytes(grid: Grid, geom: Geometry, npart: int, ckpt_every: int,
+                                 live_pairs: int = 0) -> int:
+    g, ge = grid.c(), geom.c()
+    nbytes = ctypes.c_size_t()
+    _check(lib().vip_grad_logpost_workspace(ctypes.byref(g), ctypes.byref(ge), npart,
+                                            ckpt_every, live_pairs, ctypes.byref(nbytes)),
+           "vip_grad_logpost_workspace")
+    return nbytes.value
+
+
+def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
+                     dobs: torch.Tensor, sigma: float, ckpt_every: int = 50,
+                     lo: Optional[torch.Tensor] = None, hi: Optional[torch.Tensor] = None,
+                     live_pairs: int = 0, logpost: Optional[torch.Tensor] = None,
+                     grad: Optional[torch.Tensor] = None, ws_tag: str = "grad"):
+    ctx.sync_stream()
+    npart = vel.shape[0]
+    nbytes = grad_logpost_workspace_bytes(grid, geom, npart, ckpt_every, live_pairs)
+    ws = ctx.workspace(ws_tag, nbytes)
+    if logpost is None:
+        logpost = torch.empty(npart, dtype=torch.float64, device=ctx.device)
+    if grad is None:
+        grad = torch.empty_like(vel)
+    g, ge = grid.c(), geom.c()
+    pr = _prior(lo, hi)
+    _check(lib().vip_grad_logpost(ctx.handle, ctypes.byref(g), ctypes.byref(ge),
+                                  ctypes.byref(pr) if pr is not None else None, npart,
+                                  _ptr(vel, torch.float32), _ptr(dobs, torch.float32), sigma,
+                                  ckpt_every, live_pairs, _ptr(logpost, torch.float64),
+                                  _ptr(grad, torch.float32), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel()), "vip_grad_logpost")
+    return logpost, grad
+
+
+def vip_grad_logpost_plain(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
+                           dobs: torch.Tensor, sigma: float, lo=None, hi=None):
+    ctx.sync_stream()
+    npart = vel.shape[0]
+    g, ge = grid.c(), geom.c()
+    nbytes = ctypes.c_size_t()
+    _check(lib().vip_grad_logpost_plain_workspace(ctypes.byref(g), ctypes.byref(ge), npart,
+                                                  ctypes.byref(nbytes)),
+           "vip_grad_logpost_plain_workspace")
+    ws = ctx.workspace("plain", nbytes.value)
+    logpost = torch.empty(npart, dtype=torch.float64, device=ctx.device)
+    grad = torch.empty_like(vel)
+    pr = _prior(lo, hi)
+    _check(lib().vip_grad_logpost_plain(ctx.handle, ctypes.byref(g), ctypes.byref(ge),
+                                        ctypes.byref(pr) if pr is not None else None, npart,
+                                        _ptr(vel, torch.float32), _ptr(dobs, torch.float32),
+                                        sigma, _ptr(logpost, torch.float64),
+                                        _ptr(grad, torch.float32),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel()),
+           "vip_grad_logpost_plain")
+    return logpost, grad
+
+
+def tape_sizes(grid: Grid, geom: Geometry, npart: int, ckpt_every: int):
+    g, ge = grid.c(), geom.c()
+    tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().vip_tape_bytes(ctypes.byref(g), ctypes.byref(ge), npart, ckpt_every,
+                                ctypes.byref(tb)), "vip_tape_bytes")
+    _check(lib().vip_tape_workspace(ctypes.byref(g), ctypes.byref(ge), npart, ckpt_every,
+                                    ctypes.byref(wb)), "vip_tape_workspace")
+    return tb.value, wb.value
+
+
+def vip_forward_tape(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
+                     ckpt_every: int, tape: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
+    ctx.sync_stream()
+    npart = vel.shape[0]
+    data = torch.empty((npart, geom.ns, grid.nt, geom.nr), dtype=torch.float32, device=ctx.device)
+    g, ge = grid.c(), geom.c()
+    _check(lib().vip_forward_tape(ctx.handle, ctypes.byref(g), ctypes.byref(ge), npart,
+                                  _ptr(vel, torch.float32), _ptr(data, torch.float32), ckpt_every,
+                                  ctypes.c_void_p(tape.data_ptr()), tape.numel(),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel()), "vip_forward_tape")
+    return data
+
+
+def vip_adjoint_tape(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor, ckpt_every: int,
+                     tape: torch.Tensor, grad_data: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
+    ctx.sync_stream()
+    npart = vel.shape[0]
+    grad_vel = torch.empty_like(vel)
+    g, ge = grid.c(), geom.c()
+    _check(lib().vip_adjoint_tape(ctx.handle, ctypes.byref(g), ctypes.byref(ge), npart,
+                                  _ptr(vel, torch.float32), ckpt_every,
+                                  ctypes.c_void_p(tape.data_ptr()), tape.numel(),
+                                  _ptr(grad_data, torch.float32), _ptr(grad_vel, torch.float32),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel()), "vip_adjoint_tape")
+    return grad_vel
+
+
+def svgd_workspace_bytes(n: int, d: int) -> int:
+    nbytes = ctypes.c_size_t()
+    _check(lib().vip_svgd_workspace(n, d, ctypes.byref(nbytes)), "vip_svgd_workspace")
+    return nbytes.value
+
+
+def svgd_layout(n: int, d: int) -> VipSvgdLayout:
+    lay = VipSvgdLayout()
+    _check(lib().vip_svgd_layout_of(n, d, ctypes.byref(lay)), "vip_svgd_layout_of")
+    return lay
+
+
+def vip_svgd_step(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
+                  bw_mode: int = VIP_BW_MEDIAN_ALL, h_fixed: float = 1.0,
+                  gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
+                  h2_out: Optional[torch.Tensor] = None, ws_tag: str = "svgd") -> torch.Tensor:
+    """In-place SVGD update of x ([n][d] float32); returns the workspace."""
+    ctx.sync_stream()
+    n = x.shape[0]
+    d = x.numel() // n
+    ws = ctx.workspace(ws_tag, svgd_workspace_bytes(n, d))
+    pr = _prior(lo, hi)
+    _check(lib().vip_svgd_step(ctx.handle, n, d, _ptr(x, torch.float32), _ptr(g, torch.float32),
+                               eps, bw_mode, h_fixed, gram_prec,
+                               ctypes.byref(pr) if pr is not None else None,
+                               _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel()), "vip_svgd_step")
+    return ws
+
+
+def vip_ssvgd_step(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
+                   xi: Optional[torch.Tensor] = None, seed: int = 0, stream: int = 0,
+                   bw_mode: int = VIP_BW_MEDIAN_ALL, h_fixed: float = 1.0,
+                   gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
+                   h2_out: Optional[torch.Tensor] = None, ws_tag: str = "svgd") -> torch.Tensor:
+    """In-place sSVGD update of x; returns the workspace."""
+    ctx.sync_stream()
+    n = x.shape[0]
+    d = x.numel() // n
+    ws = ctx.workspace(ws_tag, svgd_workspace_bytes(n, d))
+    pr = _prior(lo, hi)
+    _check(lib().vip_ssvgd_step(ctx.handle, n, d, _ptr(x, torch.float32), _ptr(g, torch.float32),
+                                eps, bw_mode, h_fixed, gram_prec,
+                                ctypes.byref(pr) if pr is not None else None,
+                                _ptr(xi, torch.float32), seed, stream,
+                                _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel()), "vip_ssvgd_step")
+    return ws
+
+
+def vip_philox_normals(ctx: Context, count: int, seed: int, stream: int) -> torch.Tensor:
+    ctx.sync_stream()
+    out = torch.empty(count, dtype=torch.float32, device=ctx.device)
+    _check(lib().vip_philox_normals(ctx.handle, count, seed, stream,
+                                    ctypes.c_void_p(out.data_ptr())), "vip_philox_normals")
+    return out
+
+
+def workspace_view(ws: torch.Tensor, offset: int, count: int, dtype) -> torch.Tensor:
+    """A typed view into a workspace at a byte offset (for inspecting results)."""
+    itemsize = torch.tensor([], dtype=dtype).element_size()
+    return ws[offset: offset + count * itemsize].view(dtype)

@@ -1,0 +1,643 @@
+// 2-D acoustic finite-difference modelling, its exact discrete adjoint and
+// the adjoint-state gradient of the log-posterior (paper section 4.2; adjoint
+// method of section 3), batched over every (particle, shot) pair.
+//
+// Scheme (second order in time, fourth in space, Cerjan sponge g):
+//   q^{n+1} = g (q^n + c (L u^n + f^n)),  u^{n+1} = g u^n + q^{n+1},  c = v^2 dt^2
+// which is u^{n+1} = g (2u^n + c (L u^n + f^n) - g u^{n-1}) carried in increment
+// form (q = u^{n+1} - g u^n) so FP32 keeps the small per-step change exactly
+// instead of recovering it from the difference of two large fields; the
+// Laplacian is evaluated as sum_o w_o (u_{i+o} - u_i) (the weights sum to 0),
+// which keeps the same property inside the stencil.
+//
+// Adjoint (scaled multiplier z = g c lambda) obeys the same recurrence run
+// backwards with the residual injected at the receivers:
+//   Q^j = g (Q^{j+1} + c (L z^{j+1} + R^T rho^j)),  z^j = g z^{j+1} + Q^j,
+// and the gradient is dJ/dv_pad = (2/v_pad) sum_n z^{n+1} (L u^n + f^n),
+// folded back onto the model by the transpose of the edge padding.
+//
+// Time stepping launches one kernel per step over all live pairs; each block
+// owns a 64-column x 4*RZ-row tile, stages u (the only field read at
+// neighbours) with its two-cell halo in LDS, and fuses the source injection,
+// the receiver gather (forward), the residual injection and the imaging sum
+// (adjoint), and the checkpoint writes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "vip_internal.h"
+#include "fwi_plan.h"
+
+namespace vip {
+
+enum { MODE_FWD = 0, MODE_REC = 1, MODE_ADJ = 2 };
+
+struct StepArgs {
+  int NX, NZ, N;
+  int tiles_x, tiles_per_pair, total_tiles;
+  int pair0, ns, nt, nr;
+  float cx, cz, inv_area;
+  const float *gx, *gz, *c;
+  const int *src_idx, *rrow, *rmap;
+  const float *wavelet;
+  uint32_t *status;
+  int n;          // FWD/REC: index of the input state u^n; ADJ: produces z^{n+1}
+  int zero_in;    // input state is identically zero (nothing read)
+  const float *u_in, *q_in;
+  long long in_stride;
+  float *u_out, *q_out;   // null: do not advance
+  long long out_stride;
+  float *data;            // FWD: receiver traces [pair][nt][nr]
+  long long data_stride;
+  float *seg;             // REC: a^n slot written; ADJ: a^n slot read
+  long long seg_stride;
+  const float *rho;       // ADJ: residual [pair][nt][nr]
+  long long rho_stride;
+  float *acc32;           // ADJ: FP32 imaging sum within a segment [pair][N]
+  double *acc64;          // ADJ: FP64 imaging sum across segments [pair][N]
+  long long acc64_stride;
+  int acc_first, acc_flush;
+};
+
+__device__ __forceinline__ int tile_of_block(int total_tiles) {
+  // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of tiles so that neighbouring tiles (shared halos) and
+  // the shots of one particle (shared coefficients) meet in the same L2.
+  int per = int(gridDim.x) >> 3;
+  int b = int(blockIdx.x);
+  return (b & 7) * per + (b >> 3);
+}
+
+template <int MODE, int RZ>
+__global__ __launch_bounds__(256) void fd_step(StepArgs a) {
+  constexpr int BZ = 4 * RZ;
+  constexpr int LW = 64 + 4;
+  constexpr float w1 = 4.0f / 3.0f, w2 = -1.0f / 12.0f;
+  __shared__ float tile[BZ + 4][LW];
+
+  const int t = tile_of_block(a.total_tiles);
+  if (t >= a.total_tiles) return;
+  const int lp = t / a.tiles_per_pair;
+  const int rem = t - lp * a.tiles_per_pair;
+  const int tzi = rem / a.tiles_x;
+  const int txi = rem - tzi * a.tiles_x;
+  const int x0 = txi * 64, z0 = tzi * BZ;
+  const int tx = int(threadIdx.x) & 63, ty = int(threadIdx.x) >> 6;
+  const int gp = a.pair0 + lp;
+  const int particle = gp / a.ns;
+  const int shot = gp - particle * a.ns;
+  const int NX = a.NX;
+
+  const float *uin = a.u_in + lp * a.in_stride;
+  const int x = x0 + tx;
+  const int xh = tx < 2 ? x0 - 2 + tx : x0 + 62 + tx;   // halo column for lanes 0..3
+  const int ch = tx < 2 ? tx : 64 + tx;                  // its LDS column
+  for (int r = ty; r < BZ + 4; r += 4) {
+    const int z = z0 - 2 + r;
+    const bool zin = z >= 0 && z < a.NZ;
+    float v = 0.0f;
+    if (!a.zero_in && zin && x < NX) v = uin[z * NX + x];
+    tile[r][tx + 2] = v;
+    if (tx < 4) {
+      float h = 0.0f;
+      if (!a.zero_in && zin && xh >= 0 && xh < NX) h = uin[z * NX + xh];
+      tile[r][ch] = h;
+    }
+  }
+  __syncthreads();
+  if (x >= NX) return;
+
+  const float gxv = a.gx[x];
+  const float *cp = a.c + size_t(particle) * size_t(a.N);
+  const float *qin = a.q_in + lp * a.in_stride;
+  int src = -1;
+  float src_amp = 0.0f;
+  if (MODE != MODE_ADJ) {
+    src = a.src_idx[shot];
+    src_amp = a.wavelet[a.n] * a.inv_area;
+  }
+#pragma unroll
+  for (int k = 0; k < RZ; ++k) {
+    const int r = ty * RZ + k;
+    const int z = z0 + r;
+    if (z >= a.NZ) break;
+    const int i = z * NX + x;
+    const float uc = tile[r + 2][tx + 2];
+    const float lx = w1 * ((tile[r + 2][tx + 1] - uc) + (tile[r + 2][tx + 3] - uc)) +
+                     w2 * ((tile[r + 2][tx] - uc) + (tile[r + 2][tx + 4] - uc));
+    const float lz = w1 * ((tile[r + 1][tx + 2] - uc) + (tile[r + 3][tx + 2] - uc)) +
+                     w2 * ((tile[r][tx + 2] - uc) + (tile[r + 4][tx + 2] - uc));
+    float lap = a.cx * lx + a.cz * lz;
+    int rid = -1;
+    if (MODE != MODE_REC) {
+      const int rr = a.rrow[z];
+      if (rr >= 0) rid = a.rmap[rr * NX + x];
+    }
+    if (MODE != MODE_ADJ) {
+      if (i == src) lap += src_amp;
+    } else if (rid >= 0) {
+      lap += a.rho[lp * a.rho_stride + (long long)(a.n + 1) * a.nr + rid];
+    }
+    if (MODE == MODE_REC) a.seg[lp * a.seg_stride + i] = lap;
+    const float gv = a.gz[z] * gxv;
+    const float qv = a.zero_in ? 0.0f : qin[i];
+    const float qn = gv * (qv + cp[i] * lap);
+    const float un = gv * uc + qn;
+    if (a.u_out) {
+      a.u_out[lp * a.out_stride + i] = un;
+      a.q_out[lp * a.out_stride + i] = qn;
+    }
+    if (MODE == MODE_FWD && rid >= 0) {
+      float *d = a.data + lp * a.data_stride;
+      d[(long long)(a.n + 1) * a.nr + rid] = un;
+      if (a.n == 0) d[rid] = 0.0f;   // u^0 = 0
+    }
+    if (MODE == MODE_ADJ) {
+      float img = un * a.seg[lp * a.seg_stride + i];
+      float *acc = a.acc32 + (long long)lp * a.N;
+      if (!a.acc_first) img += acc[i];
+      if (a.acc_flush)
+        a.acc64[lp * a.acc64_stride + i] += double(img);
+      else
+        acc[i] = img;
+    }
+  }
+}
+
+// c = (v_pad dt)^2 for every particle; v_pad replicates the model edges.
+__global__ void coeff_kernel(const float *vel, float *c, int np, int nx, int nz, int nb, int NX,
+                             int NZ, float dt, float vmax, uint32_t *status) {
+  long long N = (long long)NX * NZ;
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * np) return;
+  int p = int(idx / N);
+  int i = int(idx - (long long)p * N);
+  int Z = i / NX, X = i - Z * NX;
+  int iz = min(max(Z - nb, 0), nz - 1), ix = min(max(X - nb, 0), nx - 1);
+  float v = vel[(long long)p * nx * nz + (long long)iz * nx + ix];
+  if (!(v > 0.0f) || !(v <= vmax)) {
+    if (!isfinite(v)) atomicOr(status, VIP_FLAG_NONFINITE);
+    else atomicOr(status, VIP_FLAG_VMAX);
+  }
+  float vd = v * dt;
+  c[idx] = vd * vd;
+}
+
+// Cerjan profile gamma(delta) = exp(-(alpha delta)^2) along one padded axis.
+__global__ void sponge_kernel(float *g, int n, int nb, double alpha) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n + 2 * nb) return;
+  int delta = max(max(nb - k, k - (nb + n - 1)), 0);
+  double ad = alpha * double(delta);
+  g[k] = float(exp(-ad * ad));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Residual rho = (d - dobs)/sigma^2 in place and J = 1/2 sum (d - dobs)^2/sigma^2
+// per pair (FP64, fixed reduction order).
+__global__ __launch_bounds__(256) void residual_kernel(float *d, long long d_stride,
+                                                       const float *dobs, int pair0, int ns,
+                                                       long long per_pair, double inv_s2,
+                                                       double *J, uint32_t *status) {
+  __shared__ double part[4];
+  const int lp = blockIdx.x;
+  const int shot = (pair0 + lp) % ns;
+  float *dp = d + lp * d_stride;
+  const float *op = dobs + (long long)shot * per_pair;
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < per_pair; e += 256) {
+    double r = double(dp[e]) - double(op[e]);
+    acc += r * r;
+    dp[e] = float(r * inv_s2);
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double j = 0.5 * ((part[0] + part[1]) + (part[2] + part[3])) * inv_s2;
+    if (!isfinite(j)) atomicOr(status, VIP_FLAG_NONFINITE);
+    J[pair0 + lp] = j;
+  }
+}
+
+// grad[p][iz][ix] = sign * (2 / v) * sum_shots sum_{padded cells copied from (iz, ix)} acc64
+__global__ void finalize_grad_kernel(const double *acc64, const float *vel, float *grad, int np,
+                                     int ns, int nx, int nz, int nb, int NX, float sign) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long d = (long long)nx * nz;
+  if (idx >= d * np) return;
+  int p = int(idx / d);
+  int cell = int(idx - (long long)p * d);
+  int iz = cell / nx, ix = cell - iz * nx;
+  int NZ = nz + 2 * nb;
+  int r0 = (iz == 0) ? 0 : nb + iz, r1 = (iz == nz - 1) ? NZ - 1 : nb + iz;
+  int c0 = (ix == 0) ? 0 : nb + ix, c1 = (ix == nx - 1) ? NX - 1 : nb + ix;
+  long long N = (long long)NX * NZ;
+  double s = 0.0;
+  for (int sh = 0; sh < ns; ++sh) {
+    const double *a = acc64 + ((long long)p * ns + sh) * N;
+    for (int r = r0; r <= r1; ++r)
+      for (int c = c0; c <= c1; ++c) s += a[(long long)r * NX + c];
+  }
+  grad[idx] = float(double(sign) * 2.0 * s / double(vel[idx]));
+}
+
+// logpost[p] = -sum_s J[p][s] + log prior (0 inside a uniform box, -inf outside)
+__global__ __launch_bounds__(256) void logpost_kernel(const double *J, const float *vel,
+                                                      const float *lo, const float *hi, int ns,
+                                                      long long d, double *logpost,
+                                                      uint32_t *status) {
+  __shared__ int outside_s;
+  const int p = blockIdx.x;
+  if (threadIdx.x == 0) outside_s = 0;
+  __syncthreads();
+  if (lo) {
+    int out = 0;
+    for (long long e = threadIdx.x; e < d; e += 256) {
+      float v = vel[(long long)p * d + e];
+      out |= !(v >= lo[e] && v <= hi[e]);
+    }
+    if (out) atomicOr(&outside_s, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double j = 0.0;
+    for (int s = 0; s < ns; ++s) j += J[(long long)p * ns + s];
+    double lp = -j;
+    if (outside_s) lp = -INFINITY;
+    if (!isfinite(j)) atomicOr(status, VIP_FLAG_NONFINITE);
+    logpost[p] = lp;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Host side
+// --------------------------------------------------------------------------
+
+static vip_status launch_step(vip_ctx *ctx, int mode, int rz, int npairs, StepArgs &a) {
+  const int BZ = 4 * rz;
+  const int tiles_z = (a.NZ + BZ - 1) / BZ;
+  a.tiles_x = (a.NX + 63) / 64;
+  a.tiles_per_pair = a.tiles_x * tiles_z;
+  long long total = (long long)a.tiles_per_pair * npairs;
+  if (total > (1LL << 30)) return VIP_E_UNSUPPORTED;
+  a.total_tiles = int(total);
+  unsigned blocks = unsigned((total + 7) / 8 * 8);
+  dim3 grid(blocks), block(256);
+  hipStream_t s = ctx->s();
+#define VIP_STEP_CASE(M, R) \
+  if (mode == M && rz == R) { fd_step<M, R><<<grid, block, 0, s>>>(a); VIP_LAUNCH_CHECK(); return VIP_OK; }
+  VIP_STEP_CASE(MODE_FWD, 2) VIP_STEP_CASE(MODE_FWD, 4) VIP_STEP_CASE(MODE_FWD, 8)
+  VIP_STEP_CASE(MODE_REC, 2) VIP_STEP_CASE(MODE_REC, 4) VIP_STEP_CASE(MODE_REC, 8)
+  VIP_STEP_CASE(MODE_ADJ, 2) VIP_STEP_CASE(MODE_ADJ, 4) VIP_STEP_CASE(MODE_ADJ, 8)
+#undef VIP_STEP_CASE
+  return VIP_E_UNSUPPORTED;
+}
+
+static StepArgs base_args(const FwiDims &D, const FwiPlan &P, const float *wavelet, int pair0) {
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.NX = D.NX;
+  a.NZ = D.NZ;
+  a.N = int(D.N);
+  a.pair0 = pair0;
+  a.ns = D.ns;
+  a.nt = D.nt;
+  a.nr = D.nr;
+  a.cx = D.cx;
+  a.cz = D.cz;
+  a.inv_area = D.inv_area;
+  a.gx = P.gx;
+  a.gz = P.gz;
+  a.c = P.c;
+  a.src_idx = P.src;
+  a.rrow = P.rrow;
+  a.rmap = P.rmap;
+  a.wavelet = wavelet;
+  a.status = P.status;
+  return a;
+}
+
+vip_status upload_tables(vip_ctx *ctx, const FwiDims &D, const vip_grid *grid,
+                         const vip_geometry *geom, const FwiPlan &P) {
+  hipStream_t s = ctx->s();
+  sponge_kernel<<<dim3((D.NX + 255) / 256), dim3(256), 0, s>>>(P.gx, D.nx, D.nb, grid->sponge_alpha);
+  VIP_LAUNCH_CHECK();
+  sponge_kernel<<<dim3((D.NZ + 255) / 256), dim3(256), 0, s>>>(P.gz, D.nz, D.nb, grid->sponge_alpha);
+  VIP_LAUNCH_CHECK();
+  std::vector<int32_t> src(D.ns), rrow(D.NZ, -1), rmap(size_t(D.nrows) * D.NX, -1);
+  for (int k = 0; k < D.ns; ++k) src[k] = (geom->src_iz[k] + D.nb) * D.NX + geom->src_ix[k] + D.nb;
+  int rows = 0;
+  for (int r = 0; r < D.nr; ++r) {
+    int Z = geom->rec_iz[r] + D.nb;
+    if (rrow[Z] < 0) rrow[Z] = rows++;
+  }
+  for (int r = 0; r < D.nr; ++r) {
+    int Z = geom->rec_iz[r] + D.nb, X = geom->rec_ix[r] + D.nb;
+    rmap[size_t(rrow[Z]) * D.NX + X] = r;   // nodes are distinct (checked in make_dims)
+  }
+  VIP_TRY(upload_i32(s, P.src, src.data(), src.size()));
+  VIP_TRY(upload_i32(s, P.rrow, rrow.data(), rrow.size()));
+  VIP_TRY(upload_i32(s, P.rmap, rmap.data(), rmap.size()));
+  return VIP_OK;
+}
+
+vip_status launch_coeff(vip_ctx *ctx, const FwiDims &D, const vip_grid *grid, const float *vel,
+                        const FwiPlan &P) {
+  long long total = D.N * D.np;
+  coeff_kernel<<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, ctx->s()>>>(
+      vel, P.c, D.np, D.nx, D.nz, D.nb, D.NX, D.NZ, float(grid->dt), float(grid->vmax), P.status);
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+// Forward sweep for pairs [pair0, pair0 + npairs): traces into data (indexed by
+// local pair, stride nt*nr); optional checkpoints (u, q) at steps s*k, s >= 1,
+// into ckpt [pair][nseg-1][2][N].
+vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
+                         int pair0, int npairs, float *data, float *ckpt) {
+  const long long N = D.N;
+  const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
+  const float *u_in = nullptr, *q_in = nullptr;
+  long long in_stride = N;
+  for (int n = 0; n <= D.nt - 2; ++n) {
+    StepArgs a = base_args(D, P, wavelet, pair0);
+    a.n = n;
+    a.zero_in = n == 0;
+    a.u_in = n == 0 ? P.u[0] : u_in;
+    a.q_in = n == 0 ? P.q[0] : q_in;
+    a.in_stride = in_stride;
+    const int m = n + 1;
+    if (ckpt && m % D.k == 0 && m / D.k <= D.nseg - 1) {
+      a.u_out = ckpt + (long long)(m / D.k - 1) * 2 * N;
+      a.q_out = a.u_out + N;
+      a.out_stride = ck_stride;
+    } else {
+      a.u_out = P.u[m & 1];
+      a.q_out = P.q[m & 1];
+      a.out_stride = N;
+    }
+    a.data = data;
+    a.data_stride = (long long)D.nt * D.nr;
+    VIP_TRY(launch_step(ctx, MODE_FWD, D.rz, npairs, a));
+    u_in = a.u_out;
+    q_in = a.q_out;
+    in_stride = a.out_stride;
+  }
+  return VIP_OK;
+}
+
+// Backward sweep: for each segment from the last, recompute a^n = L u^n + f^n
+// from its checkpoint, then run the adjoint over the segment with the imaging
+// sum; rho [pair][nt][nr] (local pair), acc64 [pair][N] (local pair, zeroed).
+vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
+                          int pair0, int npairs, const float *rho, const float *ckpt,
+                          double *acc64) {
+  const long long N = D.N;
+  const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
+  const long long seg_stride = (long long)D.k * N;
+  int adj_steps = 0;
+  const float *z_in = nullptr, *Q_in = nullptr;
+  for (int s = D.nseg - 1; s >= 0; --s) {
+    const int n0 = s * D.k;
+    const int n1 = std::min(n0 + D.k, D.nt - 1);
+    const float *u_in = nullptr, *q_in = nullptr;
+    long long in_stride = N;
+    for (int n = n0; n < n1; ++n) {
+      StepArgs a = base_args(D, P, wavelet, pair0);
+      a.n = n;
+      if (n == n0) {
+        a.zero_in = s == 0;
+        a.u_in = s == 0 ? P.u[0] : ckpt + (long long)(s - 1) * 2 * N;
+        a.q_in = s == 0 ? P.q[0] : a.u_in + N;
+        a.in_stride = s == 0 ? N : ck_stride;
+      } else {
+        a.u_in = u_in;
+        a.q_in = q_in;
+        a.in_stride = in_stride;
+      }
+      if (n < n1 - 1) {
+        a.u_out = P.u[(n + 1) & 1];
+        a.q_out = P.q[(n + 1) & 1];
+        a.out_stride = N;
+      }
+      a.seg = P.seg + (long long)(n - n0) * N;
+      a.seg_stride = seg_stride;
+      VIP_TRY(launch_step(ctx, MODE_REC, D.rz, npairs, a));
+      u_in = a.u_out;
+      q_in = a.q_out;
+      in_stride = N;
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      StepArgs a = base_args(D, P, wavelet, pair0);
+      a.n = n;
+      a.zero_in = adj_steps == 0;
+      a.u_in = adj_steps == 0 ? P.z[0] : z_in;
+      a.q_in = adj_steps == 0 ? P.Q[0] : Q_in;
+      a.in_stride = N;
+      a.u_out = P.z[(adj_steps + 1) & 1];
+      a.q_out = P.Q[(adj_steps + 1) & 1];
+      a.out_stride = N;
+      a.rho = rho;
+      a.rho_stride = (long long)D.nt * D.nr;
+      a.seg = P.seg + (long long)(n - n0) * N;
+      a.seg_stride = seg_stride;
+      a.acc32 = P.acc32;
+      a.acc64 = acc64;
+      a.acc64_stride = N;
+      a.acc_first = n == n1 - 1;
+      a.acc_flush = n == n0;
+      VIP_TRY(launch_step(ctx, MODE_ADJ, D.rz, npairs, a));
+      z_in = a.u_out;
+      Q_in = a.q_out;
+      ++adj_steps;
+    }
+  }
+  return VIP_OK;
+}
+
+vip_status launch_residual(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, int pair0,
+                           int npairs, const float *dobs, double sigma) {
+  long long per_pair = (long long)D.nt * D.nr;
+  residual_kernel<<<dim3(npairs), dim3(256), 0, ctx->s()>>>(
+      P.resid, per_pair, dobs, pair0, D.ns, per_pair, 1.0 / (sigma * sigma), P.J, P.status);
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+vip_status launch_finalize(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
+                           float *grad, float sign) {
+  long long total = (long long)D.nx * D.nz * D.np;
+  finalize_grad_kernel<<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, ctx->s()>>>(
+      P.acc64, vel, grad, D.np, D.ns, D.nx, D.nz, D.nb, D.NX, sign);
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+vip_status launch_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
+                          const vip_prior *prior, double *logpost) {
+  const float *lo = nullptr, *hi = nullptr;
+  if (prior && prior->kind == VIP_PRIOR_UNIFORM_CLIP) {
+    lo = prior->lo;
+    hi = prior->hi;
+  }
+  logpost_kernel<<<dim3(D.np), dim3(256), 0, ctx->s()>>>(P.J, vel, lo, hi, D.ns,
+                                                         (long long)D.nx * D.nz, logpost, P.status);
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+}  // namespace vip
+
+using namespace vip;
+
+extern "C" {
+
+vip_status vip_forward_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                                 size_t *bytes) {
+  if (!bytes) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, grid ? grid->nt : 0, 0, false, &D));
+  FwiPlan P;
+  plan_fwi(D, nullptr, PLAN_FORWARD, &P);
+  *bytes = P.bytes;
+  return VIP_OK;
+}
+
+vip_status vip_forward(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                       const float *vel, float *data, void *ws, size_t ws_bytes) {
+  if (!ctx || !vel || !data || !ws) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, grid ? grid->nt : 0, 0, true, &D));
+  FwiPlan P;
+  plan_fwi(D, static_cast<char *>(ws), PLAN_FORWARD, &P);
+  if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  KeyBuilder kb;
+  kb.add(std::string("fwd")).add(*grid).add(np).add(vel).add(data).add(ws).add(geom->wavelet)
+      .add(geom->ns).add(geom->nr);
+  kb.add_array(geom->src_ix, geom->ns).add_array(geom->src_iz, geom->ns)
+      .add_array(geom->rec_ix, geom->nr).add_array(geom->rec_iz, geom->nr);
+  return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
+    VIP_TRY(upload_tables(ctx, D, grid, geom, P));
+    VIP_TRY(launch_coeff(ctx, D, grid, vel, P));
+    return forward_sweep(ctx, D, P, geom->wavelet, 0, int(D.pairs), data, nullptr);
+  });
+}
+
+vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                                      int32_t ckpt_every, int32_t live_pairs, size_t *bytes) {
+  if (!bytes) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, false, &D));
+  FwiPlan P;
+  plan_fwi(D, nullptr, PLAN_GRAD, &P);
+  *bytes = P.bytes;
+  return VIP_OK;
+}
+
+vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                            const vip_prior *prior, int32_t np, const float *vel,
+                            const float *dobs, double sigma, int32_t ckpt_every, int32_t live_pairs,
+                            double *logpost, float *grad, void *ws, size_t ws_bytes) {
+  if (!ctx || !vel || !dobs || !logpost || !grad || !ws) return VIP_E_ARG;
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return VIP_E_ARG;
+  if (prior && prior->kind != VIP_PRIOR_NONE &&
+      (prior->kind != VIP_PRIOR_UNIFORM_CLIP || !prior->lo || !prior->hi))
+    return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, true, &D));
+  FwiPlan P;
+  plan_fwi(D, static_cast<char *>(ws), PLAN_GRAD, &P);
+  if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  KeyBuilder kb;
+  kb.add(std::string("grad")).add(*grid).add(np).add(vel).add(dobs).add(sigma).add(ckpt_every)
+      .add(live_pairs).add(logpost).add(grad).add(ws).add(geom->wavelet).add(geom->ns)
+      .add(geom->nr);
+  kb.add(prior ? prior->kind : -1).add(prior ? prior->lo : nullptr).add(prior ? prior->hi : nullptr);
+  kb.add_array(geom->src_ix, geom->ns).add_array(geom->src_iz, geom->ns)
+      .add_array(geom->rec_ix, geom->nr).add_array(geom->rec_iz, geom->nr);
+  return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
+    VIP_TRY(upload_tables(ctx, D, grid, geom, P));
+    VIP_TRY(launch_coeff(ctx, D, grid, vel, P));
+    VIP_TRY(fill_f64(ctx->s(), P.acc64, size_t(D.pairs * D.N), 0.0));
+    for (long long p0 = 0; p0 < D.pairs; p0 += D.live) {
+      int cnt = int(std::min<long long>(D.live, D.pairs - p0));
+      VIP_TRY(forward_sweep(ctx, D, P, geom->wavelet, int(p0), cnt, P.resid, P.ckpt));
+      VIP_TRY(launch_residual(ctx, D, P, int(p0), cnt, dobs, sigma));
+      VIP_TRY(backward_sweep(ctx, D, P, geom->wavelet, int(p0), cnt, P.resid, P.ckpt,
+                             P.acc64 + p0 * D.N));
+    }
+    VIP_TRY(launch_finalize(ctx, D, P, vel, grad, -1.0f));
+    return launch_logpost(ctx, D, P, vel, prior, logpost);
+  });
+}
+
+vip_status vip_tape_bytes(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                          int32_t ckpt_every, size_t *bytes) {
+  if (!bytes) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, 0, false, &D));
+  *bytes = size_t(D.pairs) * size_t(D.nseg - 1) * 2 * size_t(D.N) * sizeof(float);
+  return VIP_OK;
+}
+
+vip_status vip_tape_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
+                              int32_t ckpt_every, size_t *bytes) {
+  if (!bytes) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, 0, false, &D));
+  FwiPlan P;
+  plan_fwi(D, nullptr, PLAN_TAPE, &P);
+  *bytes = P.bytes;
+  return VIP_OK;
+}
+
+vip_status vip_forward_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                            int32_t np, const float *vel, float *data, int32_t ckpt_every,
+                            void *tape, size_t tape_bytes, void *ws, size_t ws_bytes) {
+  if (!ctx || !vel || !data || !ws) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, 0, true, &D));
+  size_t need = size_t(D.pairs) * size_t(D.nseg - 1) * 2 * size_t(D.N) * sizeof(float);
+  if (tape_bytes < need || (need > 0 && !tape)) return VIP_E_WORKSPACE;
+  FwiPlan P;
+  plan_fwi(D, static_cast<char *>(ws), PLAN_TAPE, &P);
+  if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  ctx->active = ctx->user;
+  VIP_TRY(upload_tables(ctx, D, grid, geom, P));
+  VIP_TRY(launch_coeff(ctx, D, grid, vel, P));
+  return forward_sweep(ctx, D, P, geom->wavelet, 0, int(D.pairs), data,
+                       static_cast<float *>(tape));
+}
+
+vip_status vip_adjoint_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
+                            int32_t np, const float *vel, int32_t ckpt_every, const void *tape,
+                            size_t tape_bytes, const float *grad_data, float *grad_vel, void *ws,
+                            size_t ws_bytes) {
+  if (!ctx || !vel || !grad_data || !grad_vel || !ws) return VIP_E_ARG;
+  FwiDims D;
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, 0, true, &D));
+  size_t need = size_t(D.pairs) * size_t(D.nseg - 1) * 2 * size_t(D.N) * sizeof(float);
+  if (tape_bytes < need || (need > 0 && !tape)) return VIP_E_WORKSPACE;
+  FwiPlan P;
+  plan_fwi(D, static_cast<char *>(ws), PLAN_TAPE, &P);
+  if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  ctx->active = ctx->user;
+  VIP_TRY(upload_tables(ctx, D, grid, geom, P));
+  VIP_TRY(launch_coeff(ctx, D, grid, vel, P));
+  VIP_TRY(fill_f64(ctx->s(), P.acc64, size_t(D.pairs * D.N), 0.0));
+  VIP_TRY(backward_sweep(ctx, D, P, geom->wavelet, 0, int(D.pairs), grad_data,
+                         static_cast<const float *>(tape), P.acc64));
+  return launch_finalize(ctx, D, P, vel, grad_vel, 1.0f);
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""GPU parity of the FWI path (vip_forward, vip_grad_logpost) against the FP64
+oracle.  Tolerances: receiver data <= 1e-5 relative L2, gradients <= 1e-4
+relative L2 per particle, log-posterior <= 1e-5 relative.
+
+The log-posterior bound follows from the data bound: J = |r|^2 / (2 sigma^2)
+with r = d - dobs, so |dJ| / J <= 2 |dd| / |r|, and for particles drawn from
+the prior |r| is of the order of |d|."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fwi as ofwi
+from paper_2310_13325_amd import binding as vb
+from paper_2310_13325_amd import configs
+from tests.cases import build_case, small_problem, f32
+from tests.gpu_helpers import ctx, dev, grid_geom, rel
+
+pytestmark = pytest.mark.gpu
+
+WAVE_TOL = 1e-5
+GRAD_TOL = 1e-4
+LOGPOST_TOL = 1e-5
+
+
+def test_ricker_matches_oracle():
+    c = ctx()
+    w = vb.vip_ricker(c, 700, 1e-3, 10.0).cpu().numpy()
+    ref = ofwi.ricker(700, 1e-3, 10.0)
+    assert np.abs(w - ref).max() <= 1e-7
+
+
+def test_forward_c1_matches_oracle():
+    case = build_case(configs.C1)
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    models = np.stack([case.v_true, case.particles[0], case.particles[5]])
+    data = vb.vip_forward(c, grid, geom, dev(models)).cpu().numpy()
+    for p in range(models.shape[0]):
+        ref = ofwi.simulate(models[p], case.ogrid, case.ogeom)
+        e = rel(data[p], ref)
+        print(f"c1 forward model {p}: rel L2 {e:.3e}", flush=True)
+        assert e <= WAVE_TOL
+        assert np.all(data[p][:, 0, :] == 0.0)
+
+
+def _scattered_geometry(prob):
+    nx, nz = prob.nx, prob.nz
+    src = [(0, 0), (nz - 1, nx - 1), (nz // 2, nx // 3)]
+    rec = [(0, 0), (0, nx - 1), (nz - 1, 0), (nz - 1, nx - 1), (2, 5), (2, 6), (nz // 2, 0),
+           (nz // 2, nx - 1), (7, 33), (30, 64), (nz - 2, nx // 2), (11, 11)]
+    return ofwi.Geometry(src_iz=tuple(s[0] for s in src), src_ix=tuple(s[1] for s in src),
+                         rec_iz=tuple(r[0] for r in rec), rec_ix=tuple(r[1] for r in rec),
+                         f0=prob.f0)
+
+
+def test_forward_ragged_grid_scattered_receivers():
+    prob = small_problem()
+    case = build_case(prob)
+    og = _scattered_geometry(prob)
+    c = ctx()
+    grid = vb.Grid(nx=prob.nx, nz=prob.nz, nt=prob.nt, dx=prob.dx, dt=prob.dt, vmax=case.vmax,
+                   nb=prob.nb)
+    w = vb.vip_ricker(c, prob.nt, prob.dt, prob.f0)
+    geom = vb.Geometry(og.src_iz, og.src_ix, og.rec_iz, og.rec_ix, w)
+    data = vb.vip_forward(c, grid, geom, dev(case.particles)).cpu().numpy()
+    for p in range(case.particles.shape[0]):
+        ref = ofwi.simulate(case.particles[p], case.ogrid, og)
+        e = rel(data[p], ref)
+        print(f"ragged forward particle {p}: rel L2 {e:.3e}", flush=True)
+        assert e <= WAVE_TOL
+
+
+def _oracle_grad(case, parts):
+    return ofwi.grad_logpost(parts, case.ogrid, case.ogeom, case.dobs, case.sigma, case.lo, case.hi)
+
+
+def test_grad_logpost_c1_matches_oracle():
+    case = build_case(configs.C1)
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    lp, g = vb.vip_grad_logpost(c, grid, geom, dev(case.particles), dev(case.dobs), case.sigma,
+                                ckpt_every=50, lo=dev(case.lo), hi=dev(case.hi))
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    lp_ref, g_ref = _oracle_grad(case, case.particles)
+    for p in range(case.particles.shape[0]):
+        eg = rel(g[p], g_ref[p])
+        el = abs(lp[p] - lp_ref[p]) / abs(lp_ref[p])
+        print(f"c1 particle {p}: grad rel L2 {eg:.3e}, logpost rel {el:.3e}", flush=True)
+        assert eg <= GRAD_TOL and el <= LOGPOST_TOL
+    assert c.poll(c.workspace("grad", 0)) == 0
+
+
+def test_grad_ragged_segments_and_chunks():
+    prob = small_problem(nt=181)
+    case = build_case(prob)
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    args = (c, grid, geom, dev(case.particles), dev(case.dobs), case.sigma)
+    lp_a, g_a = vb.vip_grad_logpost(*args, ckpt_every=13, live_pairs=4,
+                                    lo=dev(case.lo), hi=dev(case.hi), ws_tag="g_a")
+    lp_ref, g_ref = _oracle_grad(case, case.particles)
+    g_a = g_a.cpu().numpy()
+    for p in range(case.particles.shape[0]):
+        eg = rel(g_a[p], g_ref[p])
+        print(f"ragged particle {p}: grad rel L2 {eg:.3e}", flush=True)
+        assert eg <= GRAD_TOL
+    assert np.allclose(lp_a.cpu().numpy(), lp_ref, rtol=LOGPOST_TOL, atol=0)
+    # chunking pairs does not change any arithmetic: bitwise equal
+    lp_b, g_b = vb.vip_grad_logpost(*args, ckpt_every=13, live_pairs=0,
+                                    lo=dev(case.lo), hi=dev(case.hi), ws_tag="g_b")
+    assert torch.equal(lp_b.cpu(), lp_a.cpu()) and np.array_equal(g_b.cpu().numpy(), g_a)
+    # other checkpoint intervals only regroup the FP32 segment sums
+    for k in (1, 60, 180, 500):
+        _, g_k = vb.vip_grad_logpost(*args, ckpt_every=k, lo=dev(case.lo), hi=dev(case.hi),
+                                     ws_tag=f"g_k{k}")
+        assert rel(g_k.cpu().numpy(), g_a) <= 1e-6, k
+
+
+def test_rerun_is_bitwise_identical():
+    case = build_case(configs.C1)
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    args = (c, grid, geom, dev(case.particles), dev(case.dobs), case.sigma)
+    lp1, g1 = vb.vip_grad_logpost(*args, ckpt_every=50)
+    lp1, g1 = lp1.clone(), g1.clone()
+    lp2, g2 = vb.vip_grad_logpost(*args, ckpt_every=50)
+    assert torch.equal(lp1, lp2) and torch.equal(g1, g2)
+
+
+def test_velocity_above_declared_bound_is_flagged():
+    case = build_case(configs.C1)
+    c = ctx()
+    p = case.prob
+    grid = vb.Grid(nx=p.nx, nz=p.nz, nt=p.nt, dx=p.dx, dt=p.dt, vmax=2500.0, nb=p.nb)
+    w = vb.vip_ricker(c, p.nt, p.dt, p.f0)
+    og = case.ogeom
+    geom = vb.Geometry(og.src_iz, og.src_ix, og.rec_iz, og.rec_ix, w)
+    ws = c.workspace("forward", 0)
+    c.poll(ws)
+    vb.vip_forward(c, grid, geom, dev(np.full((1, p.nz, p.nx), 2400.0)))
+    assert c.poll(c.workspace("forward", 0)) == 0
+    vb.vip_forward(c, grid, geom, dev(np.full((1, p.nz, p.nx), 2600.0)))
+    assert c.poll(c.workspace("forward", 0)) == vb.VIP_FLAG_VMAX
+
+
+def test_cfl_violation_is_rejected_before_launch():
+    case = build_case(configs.C1)
+    c = ctx()
+    p = case.prob
+    grid = vb.Grid(nx=p.nx, nz=p.nz, nt=p.nt, dx=p.dx, dt=p.dt, vmax=6200.0, nb=p.nb)
+    w = vb.vip_ricker(c, p.nt, p.dt, p.f0)
+    og = case.ogeom
+    geom = vb.Geometry(og.src_iz, og.src_ix, og.rec_iz, og.rec_ix, w)
+    with pytest.raises(vb.VipError) as e:
+        vb.vip_forward(c, grid, geom, dev(np.full((1, p.nz, p.nx), 2000.0)))
+    assert e.value.status == -2
