@@ -252,6 +252,11 @@ vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const fl
  * vip_ssvgd_step (device float [count]). */
 vip_status vip_philox_normals(vip_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream,
                               float *out);
+/* The raw Philox4x32-10 words behind vip_philox_normals: out[4q + w] = word w
+ * of the block with counter (q, stream) and key seed, q < nblocks
+ * (device uint32 [4 nblocks]). */
+vip_status vip_philox_uint32(vip_ctx *ctx, int64_t nblocks, uint64_t seed, uint64_t stream,
+                             uint32_t *out);
 
 #ifdef __cplusplus
 }

@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
             "vip_ssvgd_step": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR, vp,
                                               u64, u64, vp, vp, sz]),
             "vip_philox_normals": (ctypes.c_int, [vp, i64, u64, u64, vp]),
+            "vip_philox_uint32": (ctypes.c_int, [vp, i64, u64, u64, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name, None)
@@ -431,6 +432,14 @@ def vip_philox_normals(ctx: Context, count: int, seed: int, stream: int) -> torc
     out = torch.empty(count, dtype=torch.float32, device=ctx.device)
     _check(lib().vip_philox_normals(ctx.handle, count, seed, stream,
                                     ctypes.c_void_p(out.data_ptr())), "vip_philox_normals")
+    return out
+
+
+def vip_philox_uint32(ctx: Context, nblocks: int, seed: int, stream: int) -> torch.Tensor:
+    ctx.sync_stream()
+    out = torch.empty(4 * nblocks, dtype=torch.int32, device=ctx.device)
+    _check(lib().vip_philox_uint32(ctx.handle, nblocks, seed, stream,
+                                   ctypes.c_void_p(out.data_ptr())), "vip_philox_uint32")
     return out
 
 

@@ -1,0 +1,582 @@
+// SVGD and stochastic SVGD particle updates (paper section 2.3-2.4).
+//
+//   RBF kernel (eq:rbf)       K_ij = exp(-|x_i - x_j|^2 / (2 h^2))
+//   SVGD (eq:phi_mean)        phi_i = 1/n sum_j [K_ij g_j + K_ij (x_i - x_j) / h^2]
+//                                   = 1/n [ (K G)_i + (s_i x_i - (K X)_i) / h^2 ],  s_i = sum_j K_ij
+//   sSVGD (eq:stochastic_svgd, eq:matrixDK, eq:noise_term)
+//                             x_i <- x_i + eps phi_i + sqrt(2 eps) (L Xi)_i,  L L^T = K / n
+//   uniform prior, strategy 1 (section 3): clip to [lo, hi] after the update.
+//
+// Kernel sequence for one step:
+//   centre      xbar = mean_i x_i (FP64 sums); Xc = X - xbar in FP32 and BF16
+//   gram        partial Gram blocks of Xc Xc^T over split ranges of d:
+//               BF16 on matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation)
+//               or FP32 on the vector units
+//   reduce      G = sum of the partials (fixed order), D_ij = G_ii + G_jj - 2 G_ij
+//   median      exact k-th order statistics of the D values by 4-pass radix
+//               select on their IEEE bits (non-negative floats order like
+//               unsigned integers), then h^2 = med / (2 ln(n+1)) (1 if med = 0)
+//   rbf         K = exp(-D / (2 h^2)), row sums s (FP64 sums)
+//   cholesky    (sSVGD) L = chol(K / n) in FP64 in LDS, jitter retries
+//   update      one FP32 register-tiled GEMM pass computing K G, K Xc (and L Xi),
+//               then phi, the update and the clip in its epilogue.
+// Distances come from centred particles: D is translation invariant, and
+// centring removes the large common velocity that BF16 could not resolve.
+#include <cmath>
+#include <cstring>
+
+#include "vip_internal.h"
+#include "philox.h"
+#include "svgd_plan.h"
+
+namespace vip {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+// ---- centre ----------------------------------------------------------------
+__global__ void centre_kernel(const float *x, float *xbar, float *xc, uint16_t *xc16, int n,
+                              long long d, uint32_t *status) {
+  long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= d) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += double(x[(long long)i * d + a]);
+  float m = float(s / double(n));
+  if (!isfinite(m)) atomicOr(status, VIP_FLAG_NONFINITE);
+  xbar[a] = m;
+  for (int i = 0; i < n; ++i) {
+    float v = x[(long long)i * d + a] - m;
+    xc[(long long)i * d + a] = v;
+    xc16[(long long)i * d + a] = f32_to_bf16_rne(v);
+  }
+}
+
+// Upper-triangular block index u -> (bi, bj), bi <= bj, row-major over bi.
+__device__ __forceinline__ void upper_block(int u, int nb, int &bi, int &bj) {
+  int row = 0, rem = u;
+  while (rem >= nb - row) {
+    rem -= nb - row;
+    ++row;
+  }
+  bi = row;
+  bj = row + rem;
+}
+
+// ---- Gram, BF16 matrix cores -------------------------------------------------
+// Block 128x128 of Xc Xc^T over k in [s*kspan, (s+1)*kspan); 4 waves, each a
+// 64x64 sub-block as 2x2 MFMA 32x32 tiles.  Operand layout of
+// v_mfma_f32_32x32x16_bf16: lane l holds row (l % 32) and k = 8 (l / 32) .. +7
+// of each operand; result register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4,
+// column l % 32.
+constexpr int GB = 128;   // block edge
+constexpr int GK = 64;    // k per LDS stage
+constexpr int GKP = GK + 8;
+
+__global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, float *part, int n,
+                                                        long long d, long long kspan, int nbt) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GB][GKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GB][GKP];
+  const int nup = nbt * (nbt + 1) / 2;
+  const int split = blockIdx.x / nup;
+  int bi, bj;
+  upper_block(blockIdx.x - split * nup, nbt, bi, bj);
+  const int i0 = bi * GB, j0 = bj * GB;
+  const long long k0 = (long long)split * kspan;
+  const long long k1 = min(d, k0 + kspan);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  f32x16_t acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+  const bool vec_ok = (d % 8) == 0;
+  for (long long kb = k0; kb < k1; kb += GK) {
+    for (int it = 0; it < 4; ++it) {
+      int idx = t + it * 256;
+      int row = idx >> 3, ch = idx & 7;
+      long long kc = kb + ch * 8;
+      uint4 va = make_uint4(0, 0, 0, 0), vbv = make_uint4(0, 0, 0, 0);
+      if (vec_ok && kc + 8 <= k1) {
+        if (i0 + row < n) va = *reinterpret_cast<const uint4 *>(xc16 + (long long)(i0 + row) * d + kc);
+        if (j0 + row < n) vbv = *reinterpret_cast<const uint4 *>(xc16 + (long long)(j0 + row) * d + kc);
+      } else {
+        uint16_t ta[8], tb[8];
+        for (int e = 0; e < 8; ++e) {
+          long long k = kc + e;
+          ta[e] = (i0 + row < n && k < k1) ? xc16[(long long)(i0 + row) * d + k] : 0;
+          tb[e] = (j0 + row < n && k < k1) ? xc16[(long long)(j0 + row) * d + k] : 0;
+        }
+        __builtin_memcpy(&va, ta, 16);
+        __builtin_memcpy(&vbv, tb, 16);
+      }
+      *reinterpret_cast<uint4 *>(&As[row][ch * 8]) = va;
+      *reinterpret_cast<uint4 *>(&Bs[row][ch * 8]) = vbv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 16) {
+      bf16x8_t fa[2], fb[2];
+      for (int m = 0; m < 2; ++m) {
+        uint4 ra = *reinterpret_cast<const uint4 *>(&As[wi * 64 + m * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+        uint4 rb = *reinterpret_cast<const uint4 *>(&Bs[wj * 64 + m * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+        __builtin_memcpy(&fa[m], &ra, 16);
+        __builtin_memcpy(&fb[m], &rb, 16);
+      }
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fb[q], acc[m][q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float *P = part + (long long)split * n * n;
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 2; ++q)
+      for (int r = 0; r < 16; ++r) {
+        int row = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        int col = j0 + wj * 64 + q * 32 + (lane & 31);
+        if (row < n && col < n) P[(long long)row * n + col] = acc[m][q][r];
+      }
+}
+
+// ---- Gram, FP32 vector units -------------------------------------------------
+// Same 128x128 blocks; each thread owns an 8x8 sub-block, k staged 16 at a time.
+__global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, float *part, int n,
+                                                       long long d, long long kspan, int nbt) {
+  constexpr int BK = 16;
+  __shared__ float As[BK][GB + 4];
+  __shared__ float Bs[BK][GB + 4];
+  const int nup = nbt * (nbt + 1) / 2;
+  const int split = blockIdx.x / nup;
+  int bi, bj;
+  upper_block(blockIdx.x - split * nup, nbt, bi, bj);
+  const int i0 = bi * GB, j0 = bj * GB;
+  const long long k0 = (long long)split * kspan;
+  const long long k1 = min(d, k0 + kspan);
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  float acc[8][8];
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0f;
+  for (long long kb = k0; kb < k1; kb += BK) {
+    for (int it = 0; it < 8; ++it) {
+      int idx = t + it * 256;        // 0 .. 2047 = 128 rows x 16 k
+      int row = idx >> 4, kk = idx & 15;
+      long long k = kb + kk;
+      As[kk][row] = (i0 + row < n && k < k1) ? xc[(long long)(i0 + row) * d + k] : 0.0f;
+      Bs[kk][row] = (j0 + row < n && k < k1) ? xc[(long long)(j0 + row) * d + k] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      float av[8], bv[8];
+      for (int e = 0; e < 8; ++e) {
+        av[e] = As[kk][ty * 8 + e];
+        bv[e] = Bs[kk][tx * 8 + e];
+      }
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) acc[a][b] = fmaf(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  float *P = part + (long long)split * n * n;
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      int row = i0 + ty * 8 + a, col = j0 + tx * 8 + b;
+      if (row < n && col < n) P[(long long)row * n + col] = acc[a][b];
+    }
+}
+
+// G = sum_s part[s] in split order; entries of lower blocks mirror the upper ones.
+__global__ void gram_reduce_kernel(const float *part, float *G, int n, int splits) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  int i = int(idx / n), j = int(idx - (long long)i * n);
+  long long src = (i / GB <= j / GB) ? idx : (long long)j * n + i;
+  float s = 0.0f;
+  for (int p = 0; p < splits; ++p) s += part[(long long)p * n * n + src];
+  G[idx] = s;
+}
+
+__global__ void sqdist_kernel(const float *G, float *D, int n, uint32_t *status) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  int i = int(idx / n), j = int(idx - (long long)i * n);
+  float v = (i == j) ? 0.0f : fmaxf(G[(long long)i * n + i] + G[(long long)j * n + j] - 2.0f * G[idx], 0.0f);
+  if (!isfinite(v)) atomicOr(status, VIP_FLAG_NONFINITE);
+  D[idx] = v;
+}
+
+// ---- exact median by radix select -------------------------------------------
+// sel[0..2] = (prefix, mask, rank) for target 0, sel[3..5] for target 1.
+__global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, int offdiag,
+                                                         int shift, const uint32_t *sel,
+                                                         uint32_t *hist) {
+  __shared__ uint32_t h[2][256];
+  for (int b = threadIdx.x; b < 512; b += 256) (&h[0][0])[b] = 0;
+  __syncthreads();
+  const uint32_t p0 = sel[0], m0 = sel[1], p1 = sel[3], m1 = sel[4];
+  const long long total = (long long)n * n;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    if (offdiag) {
+      int i = int(idx / n), j = int(idx - (long long)i * n);
+      if (i >= j) continue;
+    }
+    uint32_t key = __float_as_uint(D[idx]);
+    uint32_t digit = (key >> shift) & 0xFFu;
+    if ((key & m0) == p0) atomicAdd(&h[0][digit], 1u);
+    if ((key & m1) == p1) atomicAdd(&h[1][digit], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 512; b += 256) {
+    uint32_t v = (&h[0][0])[b];
+    if (v) atomicAdd(&hist[b], v);
+  }
+}
+
+__global__ void radix_select_kernel(uint32_t *sel, uint32_t *hist, int shift) {
+  if (threadIdx.x >= 2) return;
+  const int t = threadIdx.x;
+  uint32_t *s = sel + 3 * t;
+  uint32_t k = s[2];
+  uint32_t *h = hist + 256 * t;
+  uint32_t b = 0;
+  for (; b < 255; ++b) {
+    if (k < h[b]) break;
+    k -= h[b];
+  }
+  s[0] |= b << shift;
+  s[1] |= 0xFFu << shift;
+  s[2] = k;
+}
+
+__global__ void bandwidth_kernel(const uint32_t *sel, long long count, int n, int mode,
+                                 double h_fixed, double *h2, double *h2_out) {
+  double v;
+  if (mode == VIP_BW_FIXED) {
+    v = h_fixed * h_fixed;
+  } else {
+    double med = 0.0;
+    if (count > 0) {
+      double a = double(__uint_as_float(sel[0])), b = double(__uint_as_float(sel[3]));
+      med = (count % 2 == 1) ? b : 0.5 * (a + b);
+    }
+    v = (med == 0.0) ? 1.0 : med / (2.0 * log(double(n) + 1.0));
+  }
+  h2[0] = v;
+  if (h2_out) h2_out[0] = v;
+}
+
+// ---- kernel matrix and row sums ---------------------------------------------
+__global__ __launch_bounds__(256) void rbf_kernel(const float *D, const double *h2, float *K,
+                                                  float *s, int n) {
+  __shared__ double part[4];
+  const int i = blockIdx.x;
+  const float inv = float(1.0 / (2.0 * h2[0]));
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    float k = expf(-D[(long long)i * n + j] * inv);
+    K[(long long)i * n + j] = k;
+    acc += double(k);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) s[i] = float((part[0] + part[1]) + (part[2] + part[3]));
+}
+
+// ---- Cholesky of K/n in FP64, one workgroup, matrix in LDS ---------------------
+// Right-looking: for each column k, sqrt of the pivot, scale the column below,
+// rank-1 update of the trailing lower triangle.  On a non-positive pivot, start
+// again from K/n + delta I, delta = 1e-12 trace(K/n)/n, x10 per retry.
+constexpr int kCholMax = 128;
+
+__global__ __launch_bounds__(1024) void cholesky_kernel(const float *D, const double *h2, double *L,
+                                                        float *Lf, int n, int max_retries,
+                                                        uint32_t *status) {
+  __shared__ double A[kCholMax][kCholMax + 1];
+  __shared__ int fail;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const double inv2h2 = 1.0 / (2.0 * h2[0]);
+  const double invn = 1.0 / double(n);
+  double delta = 1e-12 * (double(n) * invn) / double(n);   // trace(K/n)/n with K_ii = 1
+  int attempt = 0;
+  for (; attempt <= max_retries; ++attempt) {
+    const double jit = attempt == 0 ? 0.0 : delta;
+    for (int e = t; e < n * n; e += nt) {
+      int i = e / n, j = e - (e / n) * n;
+      double v = exp(-double(D[e]) * inv2h2) * invn;
+      A[i][j] = (i == j) ? v + jit : v;
+    }
+    if (t == 0) fail = 0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      if (t == 0) {
+        double p = A[k][k];
+        if (!(p > 0.0)) fail = 1;
+        A[k][k] = p > 0.0 ? sqrt(p) : 1.0;
+      }
+      __syncthreads();
+      if (fail) break;
+      const double piv = A[k][k];
+      for (int i = k + 1 + t; i < n; i += nt) A[i][k] /= piv;
+      __syncthreads();
+      const int m = n - k - 1;
+      for (int e = t; e < m * m; e += nt) {
+        int i = k + 1 + e / m, j = k + 1 + e % m;
+        if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!fail) break;
+    if (attempt > 0) delta *= 10.0;
+    __syncthreads();
+  }
+  const bool ok = !fail;
+  if (t == 0) {
+    if (!ok) atomicOr(status, VIP_FLAG_NOT_PD);
+    else if (attempt > 0) atomicOr(status, VIP_FLAG_JITTER);
+  }
+  for (int e = t; e < n * n; e += nt) {
+    int i = e / n, j = e - (e / n) * n;
+    double v = (ok && j <= i) ? A[i][j] : 0.0;
+    L[e] = v;
+    Lf[e] = float(v);
+  }
+}
+
+__global__ void philox_fill_kernel(float *out, long long count, uint32_t k0, uint32_t k1,
+                                   uint32_t s0, uint32_t s1) {
+  long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (4 * q >= count) return;
+  float z[4];
+  philox_normals4(uint64_t(q), k0, k1, s0, s1, z);
+  for (int k = 0; k < 4; ++k)
+    if (4 * q + k < count) out[4 * q + k] = z[k];
+}
+
+// ---- fused update GEMM --------------------------------------------------------
+// Tile 64 particles x 64 coordinates, 256 threads with 4x4 outputs each,
+// j staged 16 at a time.  Accumulates KG = K G, KX = K Xc and, with NOISE,
+// LX = L Xi; the epilogue forms phi, writes it, and updates x in place (x is
+// read only at the element this thread writes).
+template <bool NOISE>
+__global__ __launch_bounds__(256) void update_kernel(const float *K, const float *Lf,
+                                                     const float *g, const float *xc,
+                                                     const float *xi, const float *s,
+                                                     const double *h2, float *x, float *phi,
+                                                     const float *lo, const float *hi, int n,
+                                                     long long d, float eps, float noise_scale,
+                                                     uint32_t *status) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ float Ak[BK][BM + 4];
+  __shared__ float Al[NOISE ? BK : 1][BM + 4];
+  __shared__ float Bg[BK][BN + 4];
+  __shared__ float Bx[BK][BN + 4];
+  __shared__ float Bz[NOISE ? BK : 1][BN + 4];
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const long long a0 = (long long)blockIdx.x * BN;
+  const int i0 = blockIdx.y * BM;
+  float kg[4][4], kx[4][4], lz[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) kg[r][c] = kx[r][c] = lz[r][c] = 0.0f;
+  for (int j0 = 0; j0 < n; j0 += BK) {
+    for (int it = 0; it < 4; ++it) {
+      int idx = t + it * 256;             // 64 rows x 16 j
+      int ii = idx >> 4, jj = idx & 15;
+      bool ok = (i0 + ii < n) && (j0 + jj < n);
+      Ak[jj][ii] = ok ? K[(long long)(i0 + ii) * n + j0 + jj] : 0.0f;
+      if (NOISE) Al[jj][ii] = ok ? Lf[(long long)(i0 + ii) * n + j0 + jj] : 0.0f;
+      int jr = idx >> 6, ac = idx & 63;   // 16 j x 64 coordinates
+      bool okb = (j0 + jr < n) && (a0 + ac < d);
+      long long src = (long long)(j0 + jr) * d + a0 + ac;
+      Bg[jr][ac] = okb ? g[src] : 0.0f;
+      Bx[jr][ac] = okb ? xc[src] : 0.0f;
+      if (NOISE) Bz[jr][ac] = okb ? xi[src] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < BK; ++jj) {
+      float av[4], bg[4], bx[4], al[4], bz[4];
+      for (int e = 0; e < 4; ++e) {
+        av[e] = Ak[jj][ty * 4 + e];
+        bg[e] = Bg[jj][tx * 4 + e];
+        bx[e] = Bx[jj][tx * 4 + e];
+        if (NOISE) {
+          al[e] = Al[jj][ty * 4 + e];
+          bz[e] = Bz[jj][tx * 4 + e];
+        }
+      }
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          kg[r][c] = fmaf(av[r], bg[c], kg[r][c]);
+          kx[r][c] = fmaf(av[r], bx[c], kx[r][c]);
+          if (NOISE) lz[r][c] = fmaf(al[r], bz[c], lz[r][c]);
+        }
+    }
+    __syncthreads();
+  }
+  const float inv_h2 = float(1.0 / h2[0]);
+  const float inv_n = 1.0f / float(n);
+  bool bad = false;
+  for (int r = 0; r < 4; ++r) {
+    int i = i0 + ty * 4 + r;
+    if (i >= n) break;
+    const float si = s[i];
+    for (int c = 0; c < 4; ++c) {
+      long long a = a0 + tx * 4 + c;
+      if (a >= d) break;
+      long long e = (long long)i * d + a;
+      float p = (kg[r][c] + (si * xc[e] - kx[r][c]) * inv_h2) * inv_n;
+      phi[e] = p;
+      float v = x[e] + eps * p;
+      if (NOISE) v += noise_scale * lz[r][c];
+      if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
+      bad |= !isfinite(v);
+      x[e] = v;
+    }
+  }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+}
+
+// ---- host ---------------------------------------------------------------------
+
+static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                              double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                              const vip_prior *prior, bool noise, const float *xi, uint64_t seed,
+                              uint64_t stream, double *h2_out, void *ws, size_t ws_bytes) {
+  if (!ctx || !x || !g || !ws) return VIP_E_ARG;
+  if (n < 1 || d < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return VIP_E_ARG;
+  if (bw_mode < VIP_BW_MEDIAN_ALL || bw_mode > VIP_BW_FIXED) return VIP_E_ARG;
+  if (bw_mode == VIP_BW_FIXED && !(h_fixed > 0.0)) return VIP_E_ARG;
+  if (gram_prec != VIP_GRAM_BF16 && gram_prec != VIP_GRAM_FP32) return VIP_E_ARG;
+  const float *lo = nullptr, *hi = nullptr;
+  if (prior && prior->kind != VIP_PRIOR_NONE) {
+    if (prior->kind != VIP_PRIOR_UNIFORM_CLIP || !prior->lo || !prior->hi) return VIP_E_ARG;
+    lo = prior->lo;
+    hi = prior->hi;
+  }
+  if (noise && n > kCholMax) return VIP_E_UNSUPPORTED;
+  SvgdPlan P;
+  plan_svgd(n, d, static_cast<char *>(ws), &P);
+  if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  ctx->active = ctx->user;
+  hipStream_t s = ctx->user;
+  const long long nn = (long long)n * n;
+  const unsigned nn_blocks = unsigned((nn + 255) / 256);
+
+  centre_kernel<<<dim3(unsigned((d + 255) / 256)), dim3(256), 0, s>>>(x, P.xbar, P.xc, P.xc16, n,
+                                                                      d, P.status);
+  VIP_LAUNCH_CHECK();
+  const int nup = P.nbt * (P.nbt + 1) / 2;
+  dim3 ggrid(unsigned(nup * P.splits));
+  if (gram_prec == VIP_GRAM_BF16)
+    gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan, P.nbt);
+  else
+    gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, P.part, n, d, P.kspan, P.nbt);
+  VIP_LAUNCH_CHECK();
+  gram_reduce_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.part, P.G, n, P.splits);
+  VIP_LAUNCH_CHECK();
+  sqdist_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.G, P.D, n, P.status);
+  VIP_LAUNCH_CHECK();
+
+  long long count = 0;
+  if (bw_mode != VIP_BW_FIXED) {
+    count = bw_mode == VIP_BW_MEDIAN_ALL ? nn : (long long)n * (n - 1) / 2;
+    // 0-based ranks of the middle values: m/2 - 1 and m/2 for even m, m/2 twice for odd m
+    const long long r1 = count / 2, r0 = (count % 2 == 0) ? count / 2 - 1 : count / 2;
+    int32_t sel_init[6] = {0, 0, int32_t(r0), 0, 0, int32_t(r1)};
+    VIP_TRY(upload_i32(s, reinterpret_cast<int32_t *>(P.sel), sel_init, 6));
+    if (count > 0) {
+      unsigned hb = unsigned(std::min<long long>((nn + 255) / 256, 1024));
+      for (int shift = 24; shift >= 0; shift -= 8) {
+        VIP_TRY(fill_u32(s, P.hist, 512, 0u));
+        radix_hist_kernel<<<dim3(hb), dim3(256), 0, s>>>(P.D, n, bw_mode == VIP_BW_MEDIAN_OFFDIAG,
+                                                         shift, P.sel, P.hist);
+        VIP_LAUNCH_CHECK();
+        radix_select_kernel<<<dim3(1), dim3(64), 0, s>>>(P.sel, P.hist, shift);
+        VIP_LAUNCH_CHECK();
+      }
+    }
+  }
+  bandwidth_kernel<<<dim3(1), dim3(1), 0, s>>>(P.sel, count, n, bw_mode, h_fixed, P.h2, h2_out);
+  VIP_LAUNCH_CHECK();
+  rbf_kernel<<<dim3(n), dim3(256), 0, s>>>(P.D, P.h2, P.K, P.s, n);
+  VIP_LAUNCH_CHECK();
+
+  dim3 ugrid(unsigned((d + 63) / 64), unsigned((n + 63) / 64));
+  if (noise) {
+    cholesky_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, P.Lf, n, 6, P.status);
+    VIP_LAUNCH_CHECK();
+    const float *xin = xi;
+    if (!xin) {
+      long long count_xi = (long long)n * d;
+      philox_fill_kernel<<<dim3(unsigned(((count_xi + 3) / 4 + 255) / 256)), dim3(256), 0, s>>>(
+          P.xi, count_xi, uint32_t(seed), uint32_t(seed >> 32), uint32_t(stream),
+          uint32_t(stream >> 32));
+      VIP_LAUNCH_CHECK();
+      xin = P.xi;
+    }
+    update_kernel<true><<<ugrid, dim3(256), 0, s>>>(P.K, P.Lf, g, P.xc, xin, P.s, P.h2, x, P.phi,
+                                                    lo, hi, n, d, float(eps),
+                                                    float(std::sqrt(2.0 * eps)), P.status);
+  } else {
+    update_kernel<false><<<ugrid, dim3(256), 0, s>>>(P.K, nullptr, g, P.xc, nullptr, P.s, P.h2, x,
+                                                     P.phi, lo, hi, n, d, float(eps), 0.0f,
+                                                     P.status);
+  }
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+}  // namespace vip
+
+using namespace vip;
+
+extern "C" {
+
+vip_status vip_svgd_workspace(int32_t n, int64_t d, size_t *bytes) {
+  if (!bytes || n < 1 || d < 1) return VIP_E_ARG;
+  SvgdPlan P;
+  plan_svgd(n, d, nullptr, &P);
+  *bytes = P.bytes;
+  return VIP_OK;
+}
+
+vip_status vip_svgd_layout_of(int32_t n, int64_t d, vip_svgd_layout *out) {
+  if (!out || n < 1 || d < 1) return VIP_E_ARG;
+  SvgdPlan P;
+  char *base = reinterpret_cast<char *>(kAlign);   // any aligned base; offsets only
+  plan_svgd(n, d, base, &P);
+  auto off = [&](const void *p) { return size_t(reinterpret_cast<const char *>(p) - base); };
+  out->D = off(P.D);
+  out->K = off(P.K);
+  out->h2 = off(P.h2);
+  out->L = off(P.L);
+  out->phi = off(P.phi);
+  return VIP_OK;
+}
+
+vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
+                         int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                         const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes) {
+  return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr, 0, 0,
+                     h2_out, ws, ws_bytes);
+}
+
+vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
+                          int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                          const vip_prior *prior, const float *xi, uint64_t seed, uint64_t stream,
+                          double *h2_out, void *ws, size_t ws_bytes) {
+  return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, true, xi, seed,
+                     stream, h2_out, ws, ws_bytes);
+}
+
+}  // extern "C"

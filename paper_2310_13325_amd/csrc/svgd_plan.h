@@ -1,0 +1,56 @@
+// Workspace layout of the SVGD / sSVGD step.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+
+#include "vip_internal.h"
+
+namespace vip {
+
+struct SvgdPlan {
+  uint32_t *status = nullptr;
+  float *xbar = nullptr, *xc = nullptr;
+  uint16_t *xc16 = nullptr;
+  float *part = nullptr, *G = nullptr, *D = nullptr, *K = nullptr, *s = nullptr;
+  uint32_t *hist = nullptr, *sel = nullptr;
+  double *h2 = nullptr, *L = nullptr;
+  float *Lf = nullptr, *xi = nullptr, *phi = nullptr;
+  int nbt = 0, splits = 0;
+  long long kspan = 0;
+  size_t bytes = 0;
+};
+
+// Gram blocks are 128 x 128 (upper triangle only); the contraction over d is
+// split so that about 512 workgroups run, each over at least 256 coordinates.
+inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
+  P->nbt = (n + 127) / 128;
+  const int nup = P->nbt * (P->nbt + 1) / 2;
+  int splits = std::max(1, std::min(64, (512 + nup - 1) / nup));
+  long long span = (d + splits - 1) / splits;
+  span = std::max<long long>(256, (span + 63) / 64 * 64);
+  P->kspan = span;
+  P->splits = int((d + span - 1) / span);
+  const size_t nn = size_t(n) * size_t(n), nd = size_t(n) * size_t(d);
+  Arena A;
+  A.base = base;
+  P->status = reinterpret_cast<uint32_t *>(base);
+  P->xbar = A.take<float>(size_t(d));
+  P->xc = A.take<float>(nd);
+  P->xc16 = A.take<uint16_t>(nd);
+  P->part = A.take<float>(size_t(P->splits) * nn);
+  P->G = A.take<float>(nn);
+  P->D = A.take<float>(nn);
+  P->K = A.take<float>(nn);
+  P->s = A.take<float>(size_t(n));
+  P->hist = A.take<uint32_t>(512);
+  P->sel = A.take<uint32_t>(8);
+  P->h2 = A.take<double>(1);
+  P->L = A.take<double>(nn);
+  P->Lf = A.take<float>(nn);
+  P->xi = A.take<float>(nd);
+  P->phi = A.take<float>(nd);
+  P->bytes = A.bytes();
+}
+
+}  // namespace vip

@@ -79,6 +79,15 @@ __global__ void philox_normals_kernel(float *out, int64_t count, uint32_t k0, ui
     if (4 * q + k < count) out[4 * q + k] = z[k];
 }
 
+__global__ void philox_words_kernel(uint32_t *out, int64_t nblocks, uint32_t k0, uint32_t k1,
+                                    uint32_t s0, uint32_t s1) {
+  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nblocks) return;
+  uint32_t c[4] = {uint32_t(q), uint32_t(uint64_t(q) >> 32), s0, s1};
+  philox4x32_10(c, k0, k1);
+  for (int w = 0; w < 4; ++w) out[4 * q + w] = c[w];
+}
+
 }  // namespace vip
 
 using namespace vip;
@@ -179,6 +188,17 @@ vip_status vip_philox_normals(vip_ctx *ctx, int64_t count, uint64_t seed, uint64
   int64_t quads = (count + 3) / 4;
   philox_normals_kernel<<<dim3(unsigned((quads + 255) / 256)), dim3(256), 0, ctx->user>>>(
       out, count, uint32_t(seed), uint32_t(seed >> 32), uint32_t(stream), uint32_t(stream >> 32));
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+vip_status vip_philox_uint32(vip_ctx *ctx, int64_t nblocks, uint64_t seed, uint64_t stream,
+                             uint32_t *out) {
+  if (!ctx || !out || nblocks < 0) return VIP_E_ARG;
+  if (nblocks == 0) return VIP_OK;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  philox_words_kernel<<<dim3(unsigned((nblocks + 255) / 256)), dim3(256), 0, ctx->user>>>(
+      out, nblocks, uint32_t(seed), uint32_t(seed >> 32), uint32_t(stream), uint32_t(stream >> 32));
   VIP_LAUNCH_CHECK();
   return VIP_OK;
 }

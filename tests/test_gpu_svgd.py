@@ -1,0 +1,182 @@
+"""GPU parity of the SVGD / sSVGD update (vip_svgd_step, vip_ssvgd_step) against
+the FP64 oracle, and of the Philox generator against the oracle's.
+
+Tolerances (relative L2 unless stated):
+  FP32 Gram: D <= 1e-5, K <= 1e-5, phi <= 1e-4, x' <= 1e-6 (x' ~ 3e3, update ~ 1e1);
+  BF16 Gram (d >= 4096): D <= 2e-4, K <= 2e-3, phi <= 2e-3, x' <= 1e-5.
+BF16 keeps 8 significant bits: the centred coordinates carry a relative
+rounding error of about 1e-3 each, which averages to about 2e-3/sqrt(d) in a
+squared distance, and K amplifies a relative error of D by D / (2 h^2)
+(about ln(n+1) at the median).
+The median bandwidth is checked exactly: h^2 must equal the median rule applied
+to the library's own distance matrix, so the radix select is pinned bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import philox as ophilox
+from oracle import svgd as osvgd
+from paper_2310_13325_amd import binding as vb
+from tests.gpu_helpers import ctx, dev, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _ensemble(n, d, seed, spread=100.0, base=3000.0):
+    r = np.random.default_rng(seed)
+    X = base + spread * r.standard_normal((n, d))
+    G = -(X - base) / spread ** 2 + 0.01 * r.standard_normal((n, d))
+    f = lambda a: a.astype(np.float32).astype(np.float64)
+    return f(X), f(G)
+
+
+def _inspect(ws, n, d):
+    lay = vb.svgd_layout(n, d)
+    D = vb.workspace_view(ws, lay.D, n * n, torch.float32).cpu().numpy().reshape(n, n)
+    K = vb.workspace_view(ws, lay.K, n * n, torch.float32).cpu().numpy().reshape(n, n)
+    h2 = float(vb.workspace_view(ws, lay.h2, 1, torch.float64).cpu().numpy()[0])
+    phi = vb.workspace_view(ws, lay.phi, n * d, torch.float32).cpu().numpy().reshape(n, d)
+    L = vb.workspace_view(ws, lay.L, n * n, torch.float64).cpu().numpy().reshape(n, n)
+    return D, K, h2, phi, L
+
+
+def _run(n, d, seed, gram, eps=50.0, mode=vb.VIP_BW_MEDIAN_ALL, prior=False):
+    X, G = _ensemble(n, d, seed)
+    lo = hi = None
+    if prior:
+        lo = np.full(d, 2990.0, dtype=np.float32).astype(np.float64)
+        hi = np.full(d, 3010.0, dtype=np.float32).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    h2o = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = vb.vip_svgd_step(c, x, dev(G), eps, bw_mode=mode, gram_prec=gram,
+                          lo=None if lo is None else dev(lo), hi=None if hi is None else dev(hi),
+                          h2_out=h2o, ws_tag=f"svgd{n}_{d}")
+    D, K, h2, phi, _ = _inspect(ws, n, d)
+    Xn = x.cpu().numpy().astype(np.float64)
+    assert h2o.item() == h2
+    Xr, info = osvgd.svgd_step(X, G, eps, lo, hi, mode=mode)
+    return dict(D=D, K=K, h2=h2, phi=phi, X=Xn), dict(D=info["D"], K=info["K"], h2=info["h2"],
+                                                      phi=info["phi"], X=Xr), c, ws
+
+
+def _median_rule(D, n, mode):
+    vals = D[np.triu_indices(n, 1)] if mode == vb.VIP_BW_MEDIAN_OFFDIAG else D.ravel()
+    med = float(np.median(vals.astype(np.float64))) if vals.size else 0.0
+    return 1.0 if med == 0.0 else med / (2.0 * math.log(n + 1.0))
+
+
+@pytest.mark.parametrize("n,d", [(7, 37), (64, 1000), (130, 515), (300, 777)])
+def test_svgd_fp32_gram_matches_oracle(n, d):
+    g, r, c, ws = _run(n, d, seed=n + d, gram=vb.VIP_GRAM_FP32)
+    print(f"fp32 n={n} d={d}: D {rel(g['D'], r['D']):.2e} K {rel(g['K'], r['K']):.2e} "
+          f"phi {rel(g['phi'], r['phi']):.2e} X {rel(g['X'], r['X']):.2e}", flush=True)
+    assert rel(g["D"], r["D"]) <= 1e-5
+    assert rel(g["K"], r["K"]) <= 1e-5
+    assert rel(g["phi"], r["phi"]) <= 1e-4
+    assert rel(g["X"], r["X"]) <= 1e-6
+    assert g["h2"] == pytest.approx(_median_rule(g["D"], n, vb.VIP_BW_MEDIAN_ALL), rel=1e-15)
+    assert abs(g["h2"] - r["h2"]) <= 1e-5 * r["h2"]
+    assert np.all(np.diag(g["D"]) == 0) and np.array_equal(g["D"], g["D"].T)
+    assert c.poll(ws) == 0
+
+
+@pytest.mark.parametrize("n,d", [(8, 4096), (128, 4096), (300, 4100)])
+def test_svgd_bf16_gram_matches_oracle(n, d):
+    g, r, c, ws = _run(n, d, seed=3 * n + d, gram=vb.VIP_GRAM_BF16)
+    eD, eK, ep, eX = (rel(g[k], r[k]) for k in ("D", "K", "phi", "X"))
+    print(f"bf16 n={n} d={d}: D {eD:.2e} K {eK:.2e} phi {ep:.2e} X {eX:.2e}", flush=True)
+    assert eD <= 2e-4 and eK <= 2e-3 and ep <= 2e-3 and eX <= 1e-5
+    assert g["h2"] == pytest.approx(_median_rule(g["D"], n, vb.VIP_BW_MEDIAN_ALL), rel=1e-15)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 6])
+def test_median_modes_small_n(n):
+    k12 = {vb.VIP_BW_MEDIAN_ALL: 1.0 / 9.0, vb.VIP_BW_MEDIAN_OFFDIAG: 1.0 / 3.0}
+    for mode in (vb.VIP_BW_MEDIAN_ALL, vb.VIP_BW_MEDIAN_OFFDIAG):
+        g, r, _, _ = _run(n, 33, seed=11 * n, gram=vb.VIP_GRAM_FP32, mode=mode)
+        assert g["h2"] == pytest.approx(_median_rule(g["D"], n, mode), rel=1e-15)
+        assert rel(g["X"], r["X"]) <= 1e-6
+        if n == 1:
+            assert g["h2"] == 1.0 and g["K"][0, 0] == 1.0
+        if n == 2:
+            assert abs(g["K"][0, 1] - k12[mode]) <= 1e-6
+
+
+def test_fixed_bandwidth_and_clip():
+    n, d = 9, 50
+    X, G = _ensemble(n, d, 5, spread=5.0)
+    c = ctx()
+    lo = np.full(d, 2995.0)
+    hi = np.full(d, 3005.0)
+    x = dev(X)
+    vb.vip_svgd_step(c, x, dev(G), 2000.0, bw_mode=vb.VIP_BW_FIXED, h_fixed=7.0,
+                     gram_prec=vb.VIP_GRAM_FP32, lo=dev(lo), hi=dev(hi), ws_tag="svgd_fixed")
+    Xr, info = osvgd.svgd_step(X, G, 2000.0, lo, hi, mode=osvgd.BW_FIXED, h_fixed=7.0)
+    xg = x.cpu().numpy()
+    assert np.all(xg >= 2995.0) and np.all(xg <= 3005.0)
+    assert np.any(xg == 2995.0) or np.any(xg == 3005.0)
+    assert rel(xg, Xr) <= 1e-6
+
+
+def test_ssvgd_with_given_normals_matches_oracle():
+    n, d, eps = 24, 3001, 20.0
+    X, G = _ensemble(n, d, 21)
+    xi = np.random.default_rng(22).standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), eps, xi=dev(xi), gram_prec=vb.VIP_GRAM_FP32,
+                           ws_tag="ssvgd")
+    D, K, h2, phi, L = _inspect(ws, n, d)
+    Xr, info = osvgd.ssvgd_step(X, G, eps, xi)
+    eL = rel(L, info["L"])
+    eX = rel(x.cpu().numpy(), Xr)
+    print(f"ssvgd: L {eL:.2e} X {eX:.2e}", flush=True)
+    assert eL <= 1e-5 and eX <= 1e-6
+    assert np.allclose(L, np.tril(L)) and np.all(np.diag(L) > 0)
+    assert c.poll(ws) == 0
+
+
+def test_ssvgd_coincident_particles_need_jitter():
+    n, d = 6, 40
+    X = np.full((n, d), 2500.0)
+    G = np.zeros((n, d))
+    c = ctx()
+    x = dev(X)
+    xi = np.random.default_rng(3).standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), 1.0, xi=dev(xi), gram_prec=vb.VIP_GRAM_FP32,
+                           ws_tag="ssvgd_j")
+    flags = c.poll(ws)
+    _, _, h2, _, L = _inspect(ws, n, d)
+    Xr, info = osvgd.ssvgd_step(X, G, 1.0, xi)
+    assert info["retries"] >= 1 and flags == vb.VIP_FLAG_JITTER and h2 == 1.0
+    assert np.abs(L @ L.T - np.ones((n, n)) / n).max() <= 1e-6
+    assert rel(x.cpu().numpy(), Xr) <= 1e-5
+
+
+def test_ssvgd_philox_noise_is_reproducible_and_normal():
+    n, d = 16, 2000
+    X, G = _ensemble(n, d, 31)
+    c = ctx()
+    x1, x2, x3 = dev(X), dev(X), dev(X)
+    for x, seed in ((x1, 5), (x2, 5), (x3, 6)):
+        vb.vip_ssvgd_step(c, x, dev(G), 10.0, xi=None, seed=seed, stream=9,
+                          gram_prec=vb.VIP_GRAM_FP32, ws_tag="ssvgd_p")
+    assert torch.equal(x1, x2) and not torch.equal(x1, x3)
+    xi = ophilox.normals(n * d, 5, 9).reshape(n, d)
+    Xr, _ = osvgd.ssvgd_step(X, G, 10.0, xi)
+    assert rel(x1.cpu().numpy(), Xr) <= 1e-6
+
+
+def test_philox_words_bitwise_and_normals():
+    c = ctx()
+    seed, stream = 0x0123456789ABCDEF, 0xFEDCBA9876543210
+    words = vb.vip_philox_uint32(c, 1000, seed, stream).cpu().numpy().view(np.uint32)
+    ref = np.array([ophilox.uint_block(q, seed, stream) for q in range(1000)], dtype=np.uint32)
+    assert np.array_equal(words.reshape(1000, 4), ref)
+    z = vb.vip_philox_normals(c, 4003, seed, stream).cpu().numpy()
+    zr = ophilox.normals(4003, seed, stream)
+    assert np.abs(z - zr).max() <= 2e-5
