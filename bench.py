@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Throughput of the batched SVGD-FWI hot path on one MI355X.
+
+One step = the whole hot path over one batch: the log-posterior gradient of
+every particle (2-D acoustic FD forward with checkpoints, recompute and adjoint
+sweeps, imaging, shot sum; vip_grad_logpost) followed by one stochastic SVGD
+update of the ensemble (median-bandwidth RBF kernel with the Gram on BF16
+matrix cores, kernel-weighted gradients and repulsion, Cholesky-correlated
+noise, prior clip; vip_ssvgd_step).
+
+Workload: 200 x 120 cells at 20 m (+ 20-cell sponge), nt = 2000 at 2 ms,
+10 shots at 20 m depth, 200 receivers at 360 m, 8 Hz Ricker, 128 particles,
+checkpoints every 50 steps; synthetic faulted velocity model, data from the
+library's own forward simulation plus 2 % noise, particles from the uniform
+prior.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is particle-gradients per second (one
+particle-gradient = one particle's forward + adjoint over all its shots, the
+paper's unit of cost); the line also carries the plain per-pair GPU path, the
+SVGD step rate at n = 2048, d = 24000, the roofline of the time-stepping
+kernel and the FP64 oracle timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle gradients/s (fwd+adjoint) + SVGD steps/s vs plain path, at stated err"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per padded grid point per pair per launch of the
+# time-stepping kernel: read u, q, c and write u, q (20 B); the recompute also
+# writes L u + f (4 B); the adjoint also reads it (4 B) and updates the FP32
+# segment imaging sum (8 B).
+BYTES_PER_POINT_STEP = {"forward": 20.0, "recompute": 24.0, "adjoint": 32.0}
+COUNTERS = os.path.join(ROOT, "profiles", "fd_step_c2_counters.json")
+STEP_SOURCE = os.path.join(ROOT, "paper_2310_13325_amd", "csrc", "fwi.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    with open(STEP_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_counters():
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256_16") != source_hash():
+        return None
+    return c.get("traffic_bytes_per_launch")
+
+
+def setup(prob, ctx, vb, synth, torch, npart):
+    import numpy as np
+    v, vbg = synth.true_model(prob)
+    lo, hi = synth.prior_bounds(prob, v, vbg)
+    parts = np.clip(synth.initial_particles(prob, lo, hi, npart), lo, hi)
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    grid = vb.Grid(nx=prob.nx, nz=prob.nz, nt=prob.nt, dx=prob.dx, dt=prob.dt,
+                   vmax=float(np.float32(hi.max())), nb=prob.nb, sponge_alpha=prob.alpha)
+    w = vb.vip_ricker(ctx, prob.nt, prob.dt, prob.f0)
+    geom = vb.Geometry([prob.src_iz] * prob.ns, prob.src_ix, [prob.rec_iz] * prob.nr,
+                       prob.rec_ix, w)
+    clean = vb.vip_forward(ctx, grid, geom, f32(v[None]))[0]
+    sigma = 0.02 * float(clean.abs().amax(dim=1).median())
+    dobs = (clean + sigma * f32(synth.noise(prob))).contiguous()
+    return dict(grid=grid, geom=geom, x=f32(parts), lo=f32(lo), hi=f32(hi), dobs=dobs,
+                sigma=sigma, v_true=v, lo_np=lo, hi_np=hi, parts=parts)
+
+
+def cpu_baseline(prob, S, ctx, vb, torch, workers):
+    """The FP64 oracle (a process per shot) on one particle of the workload,
+    plus the GPU's error against it on the same inputs."""
+    import numpy as np
+    from oracle import cpu_pool
+    from oracle import fwi as ofwi
+    grid = ofwi.Grid(nz=prob.nz, nx=prob.nx, nb=prob.nb, nt=prob.nt, dx=prob.dx, dz=prob.dx,
+                     dt=prob.dt, alpha=prob.alpha)
+    geom = ofwi.Geometry(src_iz=(prob.src_iz,) * prob.ns, src_ix=prob.src_ix,
+                         rec_iz=(prob.rec_iz,) * prob.nr, rec_ix=prob.rec_ix, f0=prob.f0)
+    v_true = np.float32(S["v_true"]).astype(np.float64)
+    clean = cpu_pool.simulate(v_true, grid, geom, workers)
+    sigma = 0.02 * float(np.median(np.abs(clean).max(axis=1)))
+    from paper_2310_13325_amd import synth
+    dobs = np.float32(clean + sigma * synth.noise(prob)).astype(np.float64)
+    part = np.float32(S["parts"][:1]).astype(np.float64)
+    t0 = time.perf_counter()
+    lp_ref, g_ref = cpu_pool.grad_logpost(part, grid, geom, dobs, sigma, workers)
+    wall = time.perf_counter() - t0
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    lp, g = vb.vip_grad_logpost(ctx, S["grid"], S["geom"], f32(part), f32(dobs), sigma,
+                                ckpt_every=prob.ckpt_every, ws_tag="err")
+    g = g.cpu().numpy().astype(np.float64)
+    err_g = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+    err_lp = float(abs(lp.cpu().numpy()[0] - lp_ref[0]) / abs(lp_ref[0]))
+    base = {"value": round(1.0 / wall, 5), "unit": "particle-gradients/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"1 particle x {prob.ns} shots of the workload, FP64 NumPy, one process "
+                      f"per shot on {workers} host cores, {wall:.1f} s wall"}
+    err = {"grad_rel_l2": err_g, "logpost_rel": err_lp, "against": "FP64 oracle, 1 particle"}
+    return base, err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--particles", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the gradient through a hipGraph")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); run it with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2310_13325_amd import binding as vb
+    from paper_2310_13325_amd import configs, synth
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 3}))
+        return
+
+    prob = configs.C2
+    npart = args.particles or prob.np
+    ctx = vb.Context(0, graph_mode=args.graph)
+    log(f"setup: {prob.nx}x{prob.nz}, nt={prob.nt}, {prob.ns} shots, {npart} particles")
+    S = setup(prob, ctx, vb, synth, torch, npart)
+    n, d = npart, prob.d
+    X = S["x"].view(n, d)
+    lo, hi = S["lo"].view(-1), S["hi"].view(-1)
+    logpost = torch.empty(n, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(S["x"])
+    G = grad.view(n, d)
+    eps_holder = {}
+
+    def step(i):
+        vb.vip_grad_logpost(ctx, S["grid"], S["geom"], S["x"], S["dobs"], S["sigma"],
+                            ckpt_every=prob.ckpt_every, lo=S["lo"], hi=S["hi"],
+                            logpost=logpost, grad=grad)
+        if "eps" not in eps_holder:
+            # step size giving updates of about 10 m/s (fixed after the first gradient)
+            eps_holder["eps"] = 10.0 / float(G.abs().max())
+        vb.vip_ssvgd_step(ctx, X, G, eps_holder["eps"], xi=None, seed=231013325, stream=i,
+                          gram_prec=vb.VIP_GRAM_BF16, lo=lo, hi=hi)
+
+    for i in range(args.warmup):
+        step(i)
+        log(f"warmup step {i} done")
+    torch.cuda.synchronize()
+    ctx.read_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    timing = ctx.read_timing()
+    flags = ctx.poll(ctx.workspace("grad", 0)) | ctx.poll(ctx.workspace("svgd", 0))
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; device flags {flags}")
+    if not bool(torch.isfinite(X).all()):
+        raise RuntimeError("non-finite particles after the timed steps")
+
+    value = args.steps * n / elapsed
+    kinds = {}
+    for k, t in timing.items():
+        if t["launches"]:
+            per_launch_ms = t["ms"] / t["launches"]
+            bytes_per_launch = BYTES_PER_POINT_STEP[k] * t["point_steps"] / t["launches"]
+            kinds[k] = {"launches": t["launches"], "avg_launch_us": round(per_launch_ms * 1e3, 2),
+                        "alg_GBps": round(bytes_per_launch / (per_launch_ms * 1e-3) / 1e9, 1),
+                        "share_of_step": round(t["ms"] / 1e3 / elapsed, 3)}
+    dom = max(kinds, key=lambda k: kinds[k]["share_of_step"])
+    ach = kinds[dom]["alg_GBps"]
+    traffic = traffic_from_counters()
+    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else traffic.get(dom),
+                "kernel": f"fd_step ({dom} mode)", "modes": kinds}
+
+    extra = {}
+    if not args.no_plain:
+        x1 = S["x"][:1].contiguous()
+        vb.vip_grad_logpost_plain(ctx, S["grid"], S["geom"], x1, S["dobs"], S["sigma"],
+                                  lo=S["lo"], hi=S["hi"])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        vb.vip_grad_logpost_plain(ctx, S["grid"], S["geom"], x1, S["dobs"], S["sigma"],
+                                  lo=S["lo"], hi=S["hi"])
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        extra["plain_path"] = {"value": round(1.0 / tp, 4), "unit": "particle-gradients/s",
+                               "speedup": round(value * tp, 2),
+                               "what": "one pair at a time, unfused per-step launches"}
+        log(f"plain path: {1.0 / tp:.3f} particle-gradients/s")
+    if not args.no_c5:
+        case = configs.C5
+        gen = torch.Generator(device="cuda").manual_seed(case.seed)
+        Xc = 3000.0 + case.spread * torch.randn(case.n, case.d, device="cuda", generator=gen)
+        Gc = -(Xc - 3000.0) / case.spread ** 2
+        svgd = {}
+        for name, prec in (("bf16_gram", vb.VIP_GRAM_BF16), ("fp32_gram", vb.VIP_GRAM_FP32)):
+            Xw = Xc.clone()
+            vb.vip_svgd_step(ctx, Xw, Gc, case.eps, gram_prec=prec, ws_tag="c5")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                vb.vip_svgd_step(ctx, Xw, Gc, case.eps, gram_prec=prec, ws_tag="c5")
+            torch.cuda.synchronize()
+            svgd[name] = round(reps / (time.perf_counter() - t), 2)
+        extra["svgd_steps_per_s"] = {"n": case.n, "d": case.d, **svgd}
+        log(f"svgd c5: {svgd}")
+        ctx._ws.pop("c5", None)
+
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        from oracle import cpu_pool
+        workers = min(cpu_pool.default_workers(), prob.ns)
+        log(f"cpu baseline on {workers} cores")
+        cpu, err = cpu_baseline(prob, S, ctx, vb, torch, workers)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "particle-gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "c2: FP32 batched gradients + sSVGD step; 200x120 grid at 20 m "
+                               "+ 20-cell sponge, nt=2000, dt=2 ms, 10 shots, 200 receivers, "
+                               "8 Hz Ricker, 128 particles, checkpoints every 50 steps",
+                   "particles": n, "pairs_per_step": n * prob.ns, "graph": args.graph,
+                   "gram": "bf16", "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "err": err,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

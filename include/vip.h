@@ -125,6 +125,20 @@ const char *vip_status_string(int status);
 /* Library version, major*10000 + minor*100 + patch. */
 int vip_version(void);
 
+/* Launch timing of the time-stepping kernel.  When enabled (eager mode
+ * only), every contiguous run of step-kernel launches of one kind is
+ * bracketed by HIP events on the stream it is enqueued on.  vip_read_timing
+ * synchronises, sums the runs since the last read per kind (0 = forward,
+ * 1 = recompute, 2 = adjoint) and forgets them: launches[k], ms[k] (event
+ * time of the runs) and point_steps[k] (padded grid points x pairs advanced). */
+typedef struct {
+  int64_t launches[3];
+  double ms[3];
+  double point_steps[3];
+} vip_timing;
+vip_status vip_set_timing(vip_ctx *ctx, int enable);
+vip_status vip_read_timing(vip_ctx *ctx, vip_timing *out);
+
 /* Synchronise the context stream, then read and clear the device status word
  * of a workspace previously passed to a call.  *flags gets VIP_FLAG_* bits. */
 vip_status vip_poll(vip_ctx *ctx, void *ws, uint32_t *flags);

@@ -59,6 +59,11 @@ class VipSvgdLayout(ctypes.Structure):
                 ("L", ctypes.c_size_t), ("phi", ctypes.c_size_t)]
 
 
+class VipTiming(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 3), ("ms", ctypes.c_double * 3),
+                ("point_steps", ctypes.c_double * 3)]
+
+
 class VipError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -109,6 +114,8 @@ def lib() -> ctypes.CDLL:
                                               u64, u64, vp, vp, sz]),
             "vip_philox_normals": (ctypes.c_int, [vp, i64, u64, u64, vp]),
             "vip_philox_uint32": (ctypes.c_int, [vp, i64, u64, u64, vp]),
+            "vip_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+            "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name, None)
@@ -245,6 +252,17 @@ class Context:
             ws = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
             self._ws[tag] = ws
         return ws
+
+    def set_timing(self, on: bool):
+        _check(lib().vip_set_timing(self._h, 1 if on else 0), "vip_set_timing")
+
+    def read_timing(self) -> dict:
+        """Per step-kernel kind (forward, recompute, adjoint): launches, ms, point-steps."""
+        t = VipTiming()
+        _check(lib().vip_read_timing(self._h, ctypes.byref(t)), "vip_read_timing")
+        kinds = ("forward", "recompute", "adjoint")
+        return {k: {"launches": int(t.launches[i]), "ms": float(t.ms[i]),
+                    "point_steps": float(t.point_steps[i])} for i, k in enumerate(kinds)}
 
     def poll(self, ws: torch.Tensor) -> int:
         flags = ctypes.c_uint32(0)

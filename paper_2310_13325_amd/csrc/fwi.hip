@@ -365,6 +365,7 @@ vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const
   const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
   const float *u_in = nullptr, *q_in = nullptr;
   long long in_stride = N;
+  const int run = timing_begin(ctx, MODE_FWD);
   for (int n = 0; n <= D.nt - 2; ++n) {
     StepArgs a = base_args(D, P, wavelet, pair0);
     a.n = n;
@@ -389,6 +390,7 @@ vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const
     q_in = a.q_out;
     in_stride = a.out_stride;
   }
+  timing_end(ctx, run, D.nt - 1, double(D.nt - 1) * double(N) * npairs);
   return VIP_OK;
 }
 
@@ -408,6 +410,7 @@ vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, cons
     const int n1 = std::min(n0 + D.k, D.nt - 1);
     const float *u_in = nullptr, *q_in = nullptr;
     long long in_stride = N;
+    const int run_rec = timing_begin(ctx, MODE_REC);
     for (int n = n0; n < n1; ++n) {
       StepArgs a = base_args(D, P, wavelet, pair0);
       a.n = n;
@@ -433,6 +436,8 @@ vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, cons
       q_in = a.q_out;
       in_stride = N;
     }
+    timing_end(ctx, run_rec, n1 - n0, double(n1 - n0) * double(N) * npairs);
+    const int run_adj = timing_begin(ctx, MODE_ADJ);
     for (int n = n1 - 1; n >= n0; --n) {
       StepArgs a = base_args(D, P, wavelet, pair0);
       a.n = n;
@@ -457,6 +462,7 @@ vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, cons
       Q_in = a.q_out;
       ++adj_steps;
     }
+    timing_end(ctx, run_adj, n1 - n0, double(n1 - n0) * double(N) * npairs);
   }
   return VIP_OK;
 }

@@ -88,6 +88,39 @@ __global__ void philox_words_kernel(uint32_t *out, int64_t nblocks, uint32_t k0,
   for (int w = 0; w < 4; ++w) out[4 * q + w] = c[w];
 }
 
+static hipEvent_t take_event(vip_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int timing_begin(vip_ctx *ctx, int kind) {
+  if (!ctx->timing || ctx->active != ctx->user) return -1;
+  vip_timing_run r;
+  r.start = take_event(ctx);
+  r.stop = take_event(ctx);
+  if (!r.start || !r.stop) return -1;
+  r.kind = kind;
+  r.launches = 0;
+  r.point_steps = 0.0;
+  if (hipEventRecord(r.start, ctx->active) != hipSuccess) return -1;
+  ctx->runs.push_back(r);
+  return int(ctx->runs.size()) - 1;
+}
+
+void timing_end(vip_ctx *ctx, int run, int64_t launches, double point_steps) {
+  if (run < 0) return;
+  vip_timing_run &r = ctx->runs[size_t(run)];
+  r.launches = launches;
+  r.point_steps = point_steps;
+  (void)hipEventRecord(r.stop, ctx->active);
+}
+
 }  // namespace vip
 
 using namespace vip;
@@ -139,6 +172,11 @@ vip_status vip_destroy(vip_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->user);
   (void)hipStreamSynchronize(ctx->cap);
   for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &r : ctx->runs) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -156,6 +194,32 @@ vip_status vip_set_stream(vip_ctx *ctx, void *stream) {
 vip_status vip_set_graph_mode(vip_ctx *ctx, int enable) {
   if (!ctx) return VIP_E_ARG;
   ctx->graph_mode = enable != 0;
+  return VIP_OK;
+}
+
+vip_status vip_set_timing(vip_ctx *ctx, int enable) {
+  if (!ctx) return VIP_E_ARG;
+  ctx->timing = enable != 0;
+  return VIP_OK;
+}
+
+vip_status vip_read_timing(vip_ctx *ctx, vip_timing *out) {
+  if (!ctx || !out) return VIP_E_ARG;
+  std::memset(out, 0, sizeof(*out));
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  VIP_TRY_HIP(hipStreamSynchronize(ctx->user));
+  for (auto &r : ctx->runs) {
+    float ms = 0.0f;
+    VIP_TRY_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+    if (r.kind >= 0 && r.kind < 3) {
+      out->launches[r.kind] += r.launches;
+      out->ms[r.kind] += double(ms);
+      out->point_steps[r.kind] += r.point_steps;
+    }
+    ctx->event_pool.push_back(r.start);
+    ctx->event_pool.push_back(r.stop);
+  }
+  ctx->runs.clear();
   return VIP_OK;
 }
 

@@ -69,8 +69,18 @@ struct KeyBuilder {
 
 }  // namespace vip
 
+struct vip_timing_run {
+  hipEvent_t start, stop;
+  int kind;
+  int64_t launches;
+  double point_steps;
+};
+
 struct vip_ctx {
   int device = 0;
+  bool timing = false;
+  std::vector<vip_timing_run> runs;     // recorded, not yet read
+  std::vector<hipEvent_t> event_pool;   // free events
   hipStream_t user = nullptr;   // caller's stream
   hipStream_t cap = nullptr;    // internal stream for capture / replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -117,6 +127,10 @@ vip_status run_maybe_graph(vip_ctx *ctx, const std::string &key, F &&body) {
   VIP_TRY_HIP(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
   return VIP_OK;
 }
+
+// Timing of runs of step launches (util.hip).  begin returns -1 when off.
+int timing_begin(vip_ctx *ctx, int kind);
+void timing_end(vip_ctx *ctx, int run, int64_t launches, double point_steps);
 
 // Small helpers implemented in util.hip
 vip_status fill_u32(hipStream_t s, uint32_t *p, size_t n, uint32_t v);
