@@ -120,6 +120,13 @@ vip_status vip_set_stream(vip_ctx *ctx, void *stream);
  * set and replay it afterwards (the arguments, including pointers, form the
  * cache key).  Off by default. */
 vip_status vip_set_graph_mode(vip_ctx *ctx, int enable);
+/* Shape of the time-stepping kernel.  tile = -2 (default) picks a shape per
+ * grid; -1 advances one step per launch (each block a 64 x 4*rz tile with its
+ * halo staged in LDS); 0 .. vip_tile_count()-1 select a temporally blocked
+ * shape that advances up to 4 or 8 steps per launch on an extended tile kept
+ * on chip. */
+vip_status vip_set_tile(vip_ctx *ctx, int tile);
+int vip_tile_count(void);
 /* Human-readable name of a status code (static string). */
 const char *vip_status_string(int status);
 /* Library version, major*10000 + minor*100 + patch. */

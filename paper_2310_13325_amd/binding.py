@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
             "vip_philox_normals": (ctypes.c_int, [vp, i64, u64, u64, vp]),
             "vip_philox_uint32": (ctypes.c_int, [vp, i64, u64, u64, vp]),
             "vip_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+            "vip_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
+            "vip_tile_count": (ctypes.c_int, []),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
         }
         for name, (res, args) in sig.items():
@@ -252,6 +254,10 @@ class Context:
             ws = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
             self._ws[tag] = ws
         return ws
+
+    def set_tile(self, tile: int):
+        """-2 automatic, -1 one step per launch, 0.. a temporally blocked shape."""
+        _check(lib().vip_set_tile(self._h, int(tile)), "vip_set_tile")
 
     def set_timing(self, on: bool):
         _check(lib().vip_set_timing(self._h, 1 if on else 0), "vip_set_timing")

@@ -28,6 +28,7 @@
 
 #include "vip_internal.h"
 #include "fwi_plan.h"
+#include "fd_block.h"
 
 namespace vip {
 
@@ -356,11 +357,220 @@ vip_status launch_coeff(vip_ctx *ctx, const FwiDims &D, const vip_grid *grid, co
   return VIP_OK;
 }
 
+// ---- temporally blocked sweeps -----------------------------------------------
+
+struct TileCfg {
+  int ex, ez, rz, tmax;
+};
+// Instantiated tile shapes (extended width, extended height, rows per thread,
+// steps per launch); the interior is (ex - 4 tmax) x (ez - 4 tmax).
+static const TileCfg kTiles[] = {
+    {112, 112, 14, 8},   // 0: interior 80 x 80, 896 threads
+    {80, 80, 10, 4},     // 1: interior 64 x 64, 640 threads
+    {96, 96, 12, 4},     // 2: interior 80 x 80, 768 threads
+    {64, 64, 8, 4},      // 3: interior 48 x 48, 512 threads
+    {128, 64, 8, 4},     // 4: interior 112 x 48, 1024 threads
+};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+int tile_count() { return kNumTiles; }
+
+// Default shape when no tuned choice exists: the fewest padded point-updates
+// per useful point-step (extended area / (covered interior x steps per launch),
+// with the waste of partial tiles counted).
+int default_tile(int NX, int NZ) {
+  int best = 0;
+  double best_cost = 1e300;
+  for (int c = 0; c < kNumTiles; ++c) {
+    const TileCfg &t = kTiles[c];
+    const int ix = t.ex - 4 * t.tmax, iz = t.ez - 4 * t.tmax;
+    const double tiles = double((NX + ix - 1) / ix) * double((NZ + iz - 1) / iz);
+    const double work = tiles * t.ex * t.ez / (double(NX) * NZ);
+    const double traffic = (12.0 * tiles * t.ex * t.ez / (double(NX) * NZ) + 8.0) / t.tmax;
+    const double cost = std::max(work * 25.0 / 39.3, traffic / 5.0);   // VALU ops vs HBM bytes
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return best;
+}
+
+static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, BlockArgs &a) {
+  const TileCfg &tc = kTiles[cfg];
+  const int ix = tc.ex - 4 * tc.tmax, iz = tc.ez - 4 * tc.tmax;
+  a.tiles_x = (a.NX + ix - 1) / ix;
+  a.tiles_per_pair = a.tiles_x * ((a.NZ + iz - 1) / iz);
+  const long long total = (long long)a.tiles_per_pair * npairs;
+  if (total > (1LL << 30)) return VIP_E_UNSUPPORTED;
+  a.total_tiles = int(total);
+  const dim3 grid(unsigned((total + 7) / 8 * 8)), block(unsigned(tc.ex * (tc.ez / tc.rz)));
+  hipStream_t s = ctx->s();
+#define VIP_BLOCK_CASE(C, EX, EZ, RZ, TM)                                              \
+  if (cfg == C) {                                                                      \
+    if (mode == BMODE_FWD) fd_block<BMODE_FWD, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
+    else if (mode == BMODE_REC) fd_block<BMODE_REC, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
+    else fd_block<BMODE_ADJ, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a);               \
+    VIP_LAUNCH_CHECK();                                                                \
+    return VIP_OK;                                                                     \
+  }
+  VIP_BLOCK_CASE(0, 112, 112, 14, 8)
+  VIP_BLOCK_CASE(1, 80, 80, 10, 4)
+  VIP_BLOCK_CASE(2, 96, 96, 12, 4)
+  VIP_BLOCK_CASE(3, 64, 64, 8, 4)
+  VIP_BLOCK_CASE(4, 128, 64, 8, 4)
+#undef VIP_BLOCK_CASE
+  return VIP_E_UNSUPPORTED;
+}
+
+static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wavelet, int pair0) {
+  BlockArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.NX = D.NX;
+  a.NZ = D.NZ;
+  a.N = int(D.N);
+  a.pair0 = pair0;
+  a.ns = D.ns;
+  a.nt = D.nt;
+  a.nr = D.nr;
+  a.cx = D.cx;
+  a.cz = D.cz;
+  a.inv_area = D.inv_area;
+  a.gx = P.gx;
+  a.gz = P.gz;
+  a.c = P.c;
+  a.src_idx = P.src;
+  a.rrow = P.rrow;
+  a.rmap = P.rmap;
+  a.wavelet = wavelet;
+  return a;
+}
+
+static vip_status forward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+                                        const float *wavelet, int pair0, int npairs, float *data,
+                                        float *ckpt) {
+  const long long N = D.N;
+  const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
+  const int tmax = kTiles[D.tile].tmax;
+  const float *u_in = P.u[0], *q_in = P.q[0];
+  long long in_stride = N;
+  int buf = 0, launches = 0;
+  const int run = timing_begin(ctx, MODE_FWD);
+  for (int s = 0; s < D.nseg; ++s) {
+    const int n0 = s * D.k, n1 = std::min(n0 + D.k, D.nt - 1);
+    for (int n = n0; n < n1; n += tmax) {
+      const int T = std::min(tmax, n1 - n);
+      BlockArgs a = block_args(D, P, wavelet, pair0);
+      a.steps = T;
+      a.n_start = n;
+      a.zero_in = n == 0;
+      a.u_in = u_in;
+      a.q_in = q_in;
+      a.in_stride = in_stride;
+      const int m = n + T;
+      if (ckpt && m == n1 && s + 1 <= D.nseg - 1) {
+        a.u_out = ckpt + (long long)s * 2 * N;   // checkpoint slot s+1 lives at index s
+        a.q_out = a.u_out + N;
+        a.out_stride = ck_stride;
+      } else {
+        buf ^= 1;
+        a.u_out = P.u[buf];
+        a.q_out = P.q[buf];
+        a.out_stride = N;
+      }
+      a.data = data;
+      a.data_stride = (long long)D.nt * D.nr;
+      VIP_TRY(launch_block(ctx, BMODE_FWD, D.tile, npairs, a));
+      ++launches;
+      u_in = a.u_out;
+      q_in = a.q_out;
+      in_stride = a.out_stride;
+    }
+  }
+  timing_end(ctx, run, launches, double(D.nt - 1) * double(N) * npairs);
+  return VIP_OK;
+}
+
+static vip_status backward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+                                         const float *wavelet, int pair0, int npairs,
+                                         const float *rho, const float *ckpt, double *acc64) {
+  const long long N = D.N;
+  const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
+  const long long seg_stride = (long long)D.k * N;
+  const int tmax = kTiles[D.tile].tmax;
+  bool adj_zero = true;
+  int abuf = 0;
+  for (int s = D.nseg - 1; s >= 0; --s) {
+    const int n0 = s * D.k, n1 = std::min(n0 + D.k, D.nt - 1);
+    const float *u_in = s == 0 ? P.u[0] : ckpt + (long long)(s - 1) * 2 * N;
+    const float *q_in = s == 0 ? P.q[0] : u_in + N;
+    long long in_stride = s == 0 ? N : ck_stride;
+    bool zero = s == 0;
+    int buf = 0, launches = 0;
+    const int run_rec = timing_begin(ctx, MODE_REC);
+    for (int n = n0; n < n1; n += tmax) {
+      const int T = std::min(tmax, n1 - n);
+      BlockArgs a = block_args(D, P, wavelet, pair0);
+      a.steps = T;
+      a.n_start = n;
+      a.seg_n0 = n0;
+      a.zero_in = zero;
+      a.u_in = u_in;
+      a.q_in = q_in;
+      a.in_stride = in_stride;
+      if (n + T < n1) {
+        buf ^= 1;
+        a.u_out = P.u[buf];
+        a.q_out = P.q[buf];
+        a.out_stride = N;
+      }
+      a.seg = P.seg;
+      a.seg_stride = seg_stride;
+      VIP_TRY(launch_block(ctx, BMODE_REC, D.tile, npairs, a));
+      ++launches;
+      u_in = a.u_out;
+      q_in = a.q_out;
+      in_stride = N;
+      zero = false;
+    }
+    timing_end(ctx, run_rec, launches, double(n1 - n0) * double(N) * npairs);
+    launches = 0;
+    const int run_adj = timing_begin(ctx, MODE_ADJ);
+    for (int n = n1 - 1; n >= n0; n -= tmax) {
+      const int T = std::min(tmax, n - n0 + 1);
+      BlockArgs a = block_args(D, P, wavelet, pair0);
+      a.steps = T;
+      a.n_start = n;
+      a.seg_n0 = n0;
+      a.zero_in = adj_zero;
+      a.u_in = P.z[abuf];
+      a.q_in = P.Q[abuf];
+      a.in_stride = N;
+      abuf ^= 1;
+      a.u_out = P.z[abuf];
+      a.q_out = P.Q[abuf];
+      a.out_stride = N;
+      a.rho = rho;
+      a.rho_stride = (long long)D.nt * D.nr;
+      a.seg = P.seg;
+      a.seg_stride = seg_stride;
+      a.acc64 = acc64;
+      a.acc64_stride = N;
+      VIP_TRY(launch_block(ctx, BMODE_ADJ, D.tile, npairs, a));
+      ++launches;
+      adj_zero = false;
+    }
+    timing_end(ctx, run_adj, launches, double(n1 - n0) * double(N) * npairs);
+  }
+  return VIP_OK;
+}
+
 // Forward sweep for pairs [pair0, pair0 + npairs): traces into data (indexed by
 // local pair, stride nt*nr); optional checkpoints (u, q) at steps s*k, s >= 1,
 // into ckpt [pair][nseg-1][2][N].
-vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
-                         int pair0, int npairs, float *data, float *ckpt) {
+static vip_status forward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+                                       const float *wavelet, int pair0, int npairs, float *data,
+                                       float *ckpt) {
   const long long N = D.N;
   const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
   const float *u_in = nullptr, *q_in = nullptr;
@@ -397,9 +607,9 @@ vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const
 // Backward sweep: for each segment from the last, recompute a^n = L u^n + f^n
 // from its checkpoint, then run the adjoint over the segment with the imaging
 // sum; rho [pair][nt][nr] (local pair), acc64 [pair][N] (local pair, zeroed).
-vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
-                          int pair0, int npairs, const float *rho, const float *ckpt,
-                          double *acc64) {
+static vip_status backward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+                                        const float *wavelet, int pair0, int npairs,
+                                        const float *rho, const float *ckpt, double *acc64) {
   const long long N = D.N;
   const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
   const long long seg_stride = (long long)D.k * N;
@@ -467,6 +677,19 @@ vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, cons
   return VIP_OK;
 }
 
+vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
+                         int pair0, int npairs, float *data, float *ckpt) {
+  if (D.tile < 0) return forward_sweep_stream(ctx, D, P, wavelet, pair0, npairs, data, ckpt);
+  return forward_sweep_blocked(ctx, D, P, wavelet, pair0, npairs, data, ckpt);
+}
+
+vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
+                          int pair0, int npairs, const float *rho, const float *ckpt,
+                          double *acc64) {
+  if (D.tile < 0) return backward_sweep_stream(ctx, D, P, wavelet, pair0, npairs, rho, ckpt, acc64);
+  return backward_sweep_blocked(ctx, D, P, wavelet, pair0, npairs, rho, ckpt, acc64);
+}
+
 vip_status launch_residual(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, int pair0,
                            int npairs, const float *dobs, double sigma) {
   long long per_pair = (long long)D.nt * D.nr;
@@ -504,6 +727,14 @@ using namespace vip;
 
 extern "C" {
 
+int vip_tile_count(void) { return tile_count(); }
+
+vip_status vip_set_tile(vip_ctx *ctx, int tile) {
+  if (!ctx || tile < -2 || tile >= tile_count()) return VIP_E_ARG;
+  ctx->tile = tile;
+  return VIP_OK;
+}
+
 vip_status vip_forward_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
                                  size_t *bytes) {
   if (!bytes) return VIP_E_ARG;
@@ -520,12 +751,13 @@ vip_status vip_forward(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *g
   if (!ctx || !vel || !data || !ws) return VIP_E_ARG;
   FwiDims D;
   VIP_TRY(make_dims(grid, geom, np, grid ? grid->nt : 0, 0, true, &D));
+  apply_tile_choice(ctx, &D);
   FwiPlan P;
   plan_fwi(D, static_cast<char *>(ws), PLAN_FORWARD, &P);
   if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
   VIP_TRY_HIP(hipSetDevice(ctx->device));
   KeyBuilder kb;
-  kb.add(std::string("fwd")).add(*grid).add(np).add(vel).add(data).add(ws).add(geom->wavelet)
+  kb.add(std::string("fwd")).add(D.tile).add(*grid).add(np).add(vel).add(data).add(ws).add(geom->wavelet)
       .add(geom->ns).add(geom->nr);
   kb.add_array(geom->src_ix, geom->ns).add_array(geom->src_iz, geom->ns)
       .add_array(geom->rec_ix, geom->nr).add_array(geom->rec_iz, geom->nr);
@@ -558,12 +790,13 @@ vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
     return VIP_E_ARG;
   FwiDims D;
   VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, true, &D));
+  apply_tile_choice(ctx, &D);
   FwiPlan P;
   plan_fwi(D, static_cast<char *>(ws), PLAN_GRAD, &P);
   if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
   VIP_TRY_HIP(hipSetDevice(ctx->device));
   KeyBuilder kb;
-  kb.add(std::string("grad")).add(*grid).add(np).add(vel).add(dobs).add(sigma).add(ckpt_every)
+  kb.add(std::string("grad")).add(D.tile).add(*grid).add(np).add(vel).add(dobs).add(sigma).add(ckpt_every)
       .add(live_pairs).add(logpost).add(grad).add(ws).add(geom->wavelet).add(geom->ns)
       .add(geom->nr);
   kb.add(prior ? prior->kind : -1).add(prior ? prior->lo : nullptr).add(prior ? prior->hi : nullptr);
@@ -611,6 +844,7 @@ vip_status vip_forward_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
   if (!ctx || !vel || !data || !ws) return VIP_E_ARG;
   FwiDims D;
   VIP_TRY(make_dims(grid, geom, np, ckpt_every, 0, true, &D));
+  apply_tile_choice(ctx, &D);
   size_t need = size_t(D.pairs) * size_t(D.nseg - 1) * 2 * size_t(D.N) * sizeof(float);
   if (tape_bytes < need || (need > 0 && !tape)) return VIP_E_WORKSPACE;
   FwiPlan P;
@@ -631,6 +865,7 @@ vip_status vip_adjoint_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
   if (!ctx || !vel || !grad_data || !grad_vel || !ws) return VIP_E_ARG;
   FwiDims D;
   VIP_TRY(make_dims(grid, geom, np, ckpt_every, 0, true, &D));
+  apply_tile_choice(ctx, &D);
   size_t need = size_t(D.pairs) * size_t(D.nseg - 1) * 2 * size_t(D.N) * sizeof(float);
   if (tape_bytes < need || (need > 0 && !tape)) return VIP_E_WORKSPACE;
   FwiPlan P;

@@ -18,7 +18,8 @@ struct FwiDims {
   int k, nseg;          // checkpoint interval, segments over a-indices 0 .. nt-2
   long long live;       // pairs simulated at once
   int nrows;            // distinct receiver rows
-  int rz;               // rows per thread in the step kernel (tile height 4*rz)
+  int rz;               // rows per thread in the streaming step kernel (tile height 4*rz)
+  int tile;             // temporally blocked tile shape, -1 = one step per launch
   float cx, cz, inv_area;
 };
 
@@ -29,6 +30,9 @@ inline double courant_factor(const vip_grid &g) {
 }
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int default_tile(int NX, int NZ);   // fwi.hip
+int tile_count();
 
 inline int default_rz(int NZ) { return NZ >= 96 ? 8 : (NZ >= 40 ? 4 : 2); }
 
@@ -83,6 +87,7 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
     d.nrows = int(std::unique(rows.begin(), rows.end()) - rows.begin());
   }
   d.rz = default_rz(d.NZ);
+  d.tile = default_tile(d.NX, d.NZ);
   d.cx = float(1.0 / (g.dx * g.dx));
   d.cz = float(1.0 / (g.dz * g.dz));
   d.inv_area = float(1.0 / (g.dx * g.dz));
@@ -146,6 +151,11 @@ inline void plan_fwi(const FwiDims &D, char *base, int kind, FwiPlan *P) {
     P->acc32 = A.take<float>(D.N);
   }
   P->bytes = A.bytes();
+}
+
+// The context may force a tile shape (-1 = one step per launch).
+inline void apply_tile_choice(const vip_ctx *ctx, FwiDims *D) {
+  if (ctx && ctx->tile >= -1) D->tile = ctx->tile;
 }
 
 // Implemented in fwi.hip, shared with the plain path.

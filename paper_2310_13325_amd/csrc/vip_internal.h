@@ -85,6 +85,7 @@ struct vip_ctx {
   hipStream_t cap = nullptr;    // internal stream for capture / replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool graph_mode = false;
+  int tile = -2;   // step-kernel shape: -2 automatic, -1 one step per launch, >= 0 tile table index
   std::map<std::string, hipGraphExec_t> graphs;
   // Stream the launch helpers enqueue on (user, or cap while capturing).
   hipStream_t s() const { return active; }

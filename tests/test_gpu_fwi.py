@@ -22,6 +22,9 @@ GRAD_TOL = 1e-4
 LOGPOST_TOL = 1e-5
 
 
+TILES = [-1, 0, 1, 2, 3, 4]
+
+
 def test_ricker_matches_oracle():
     c = ctx()
     w = vb.vip_ricker(c, 700, 1e-3, 10.0).cpu().numpy()
@@ -53,11 +56,13 @@ def _scattered_geometry(prob):
                          f0=prob.f0)
 
 
-def test_forward_ragged_grid_scattered_receivers():
+@pytest.mark.parametrize("tile", TILES)
+def test_forward_ragged_grid_scattered_receivers(tile):
     prob = small_problem()
     case = build_case(prob)
     og = _scattered_geometry(prob)
     c = ctx()
+    c.set_tile(tile)
     grid = vb.Grid(nx=prob.nx, nz=prob.nz, nt=prob.nt, dx=prob.dx, dt=prob.dt, vmax=case.vmax,
                    nb=prob.nb)
     w = vb.vip_ricker(c, prob.nt, prob.dt, prob.f0)
@@ -66,8 +71,9 @@ def test_forward_ragged_grid_scattered_receivers():
     for p in range(case.particles.shape[0]):
         ref = ofwi.simulate(case.particles[p], case.ogrid, og)
         e = rel(data[p], ref)
-        print(f"ragged forward particle {p}: rel L2 {e:.3e}", flush=True)
+        print(f"ragged forward tile {tile} particle {p}: rel L2 {e:.3e}", flush=True)
         assert e <= WAVE_TOL
+    c.set_tile(-2)
 
 
 def _oracle_grad(case, parts):
@@ -90,10 +96,12 @@ def test_grad_logpost_c1_matches_oracle():
     assert c.poll(c.workspace("grad", 0)) == 0
 
 
-def test_grad_ragged_segments_and_chunks():
+@pytest.mark.parametrize("tile", TILES)
+def test_grad_ragged_segments_and_chunks(tile):
     prob = small_problem(nt=181)
     case = build_case(prob)
     c = ctx()
+    c.set_tile(tile)
     grid, geom = grid_geom(c, case)
     args = (c, grid, geom, dev(case.particles), dev(case.dobs), case.sigma)
     lp_a, g_a = vb.vip_grad_logpost(*args, ckpt_every=13, live_pairs=4,
@@ -102,7 +110,7 @@ def test_grad_ragged_segments_and_chunks():
     g_a = g_a.cpu().numpy()
     for p in range(case.particles.shape[0]):
         eg = rel(g_a[p], g_ref[p])
-        print(f"ragged particle {p}: grad rel L2 {eg:.3e}", flush=True)
+        print(f"ragged tile {tile} particle {p}: grad rel L2 {eg:.3e}", flush=True)
         assert eg <= GRAD_TOL
     assert np.allclose(lp_a.cpu().numpy(), lp_ref, rtol=LOGPOST_TOL, atol=0)
     # chunking pairs does not change any arithmetic: bitwise equal
@@ -114,6 +122,7 @@ def test_grad_ragged_segments_and_chunks():
         _, g_k = vb.vip_grad_logpost(*args, ckpt_every=k, lo=dev(case.lo), hi=dev(case.hi),
                                      ws_tag=f"g_k{k}")
         assert rel(g_k.cpu().numpy(), g_a) <= 1e-6, k
+    c.set_tile(-2)
 
 
 def test_rerun_is_bitwise_identical():
