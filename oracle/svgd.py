@@ -78,16 +78,17 @@ def rbf(D: np.ndarray, h2: float) -> np.ndarray:
     return np.exp(-D / (2.0 * h2))
 
 
-def svgd_direction(X, G, mode=BW_MEDIAN_ALL, h_fixed=1.0):
+def svgd_direction(X, G, mode=BW_MEDIAN_ALL, h_fixed=1.0, D=None):
     """phi_i = 1/n [ sum_j K_ij G_j + (s_i x_i - sum_j K_ij x_j) / h^2 ],
     s_i = sum_j K_ij; the second term is sum_j grad_{m_j} k(m_j, m_i) with
     grad_{m_j} k(m_j, m_i) = K_ij (m_i - m_j) / h^2.
 
-    Returns dict(D, h2, K, s, phi)."""
+    D may be passed in when it was computed by another direct evaluation
+    (oracle.cref.sqdist for large ensembles).  Returns dict(D, h2, K, s, phi)."""
     X = np.asarray(X, dtype=np.float64)
     G = np.asarray(G, dtype=np.float64)
     n = X.shape[0]
-    D = sqdist(X)
+    D = sqdist(X) if D is None else np.asarray(D, dtype=np.float64)
     h2 = bandwidth_sq(D, mode, h_fixed)
     K = rbf(D, h2)
     s = K.sum(axis=1)

@@ -72,3 +72,23 @@ def small_problem(name="ragged", nx=70, nz=37, nt=180, ns=3, f0=18.0, dx=10.0, d
     return configs.Problem(name, nx=nx, nz=nz, dx=dx, nt=nt, dt=dt, ns=ns, np=np_, f0=f0,
                            src_iz=1, rec_iz=2, model="layers_anomalies", prior="rowmean_pm500",
                            noise="rms_1pct", seed=seed, nb=9)
+
+
+def workers():
+    from oracle import cpu_pool
+    return cpu_pool.default_workers()
+
+
+@lru_cache(maxsize=None)
+def build_case_c(prob: configs.Problem, n_particles: int | None = None) -> Case:
+    """As build_case, with the C oracle (threads) making the observed data."""
+    from oracle import cref
+    v, vb = synth.true_model(prob)
+    lo, hi = synth.prior_bounds(prob, v, vb)
+    lo, hi = f32(lo), f32(hi)
+    parts = np.clip(f32(synth.initial_particles(prob, lo, hi, n_particles)), lo, hi)
+    case = Case(prob, f32(v), lo, hi, parts, None, 0.0)
+    clean = cref.simulate(case.v_true, case.ogrid, case.ogeom, workers=workers())
+    case.sigma = sigma_of(prob, clean)
+    case.dobs = f32(clean + case.sigma * synth.noise(prob))
+    return case
