@@ -202,6 +202,39 @@ vip_status vip_grad_logpost_plain(vip_ctx *ctx, const vip_grid *grid, const vip_
                                   const float *dobs, double sigma, double *logpost, float *grad,
                                   void *ws, size_t ws_bytes);
 
+/* ---- several inversions at once ----------------------------------------- */
+
+/* One inversion problem of a batch: its grid, acquisition, prior, particles,
+ * observed data and outputs, with the same meaning as the arguments of
+ * vip_grad_logpost. */
+typedef struct {
+  vip_grid grid;
+  vip_geometry geom;
+  vip_prior prior;          /* kind VIP_PRIOR_NONE for none */
+  int32_t np;
+  const float *vel;         /* device [np][nz][nx] */
+  const float *dobs;        /* device [ns][nt][nr] */
+  double sigma;
+  double *logpost;          /* device [np] */
+  float *grad;              /* device [np][nz][nx] */
+} vip_problem;
+
+#define VIP_MAX_BATCH 4
+
+/* Workspace bytes for vip_grad_logpost_multi (all pairs of all problems live). */
+vip_status vip_grad_logpost_multi_workspace(int32_t nprob, const vip_problem *probs,
+                                            int32_t ckpt_every, size_t *bytes);
+
+/* vip_grad_logpost for 1 .. VIP_MAX_BATCH independent problems of different
+ * grid sizes, shot counts and lengths at once: every launch of the
+ * time-stepping kernel carries the next sweep step of every problem that
+ * still has one (each block finds its problem, and that problem's sweep mode,
+ * from a table in the launch arguments), with one tile shape for the batch
+ * (vip_set_tile, or chosen from the batch's estimated cost).  Results equal
+ * vip_grad_logpost on each problem alone with the same tile shape, bit for bit. */
+vip_status vip_grad_logpost_multi(vip_ctx *ctx, int32_t nprob, const vip_problem *probs,
+                                  int32_t ckpt_every, void *ws, size_t ws_bytes);
+
 /* ---- tapes: reverse-mode differentiation of vip_forward ----------------- */
 
 /* Tape bytes: the checkpointed forward states of all np*ns pairs. */
@@ -268,6 +301,27 @@ vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const fl
                           int32_t bw_mode, double h_fixed, int32_t gram_prec,
                           const vip_prior *prior, const float *xi, uint64_t seed, uint64_t stream,
                           double *h2_out, void *ws, size_t ws_bytes);
+
+/* Several independent ensembles, each updated as by vip_svgd_step or
+ * vip_ssvgd_step (ensemble e draws its Philox normals from stream + e when its
+ * xi is NULL); the workspace is shared (vip_svgd_multi_workspace) and the
+ * status word of its first bytes collects every ensemble's flags. */
+typedef struct {
+  int32_t n;
+  int64_t d;
+  float *x;                 /* device [n][d], updated in place */
+  const float *g;           /* device [n][d] */
+  double eps;
+  vip_prior prior;
+  const float *xi;          /* device [n][d] or NULL (sSVGD only) */
+  double *h2_out;           /* device [1] or NULL */
+} vip_ensemble;
+vip_status vip_svgd_multi_workspace(int32_t nens, const vip_ensemble *ens, size_t *bytes);
+vip_status vip_svgd_step_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *ens, int32_t bw_mode,
+                               double h_fixed, int32_t gram_prec, void *ws, size_t ws_bytes);
+vip_status vip_ssvgd_step_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *ens,
+                                int32_t bw_mode, double h_fixed, int32_t gram_prec, uint64_t seed,
+                                uint64_t stream, void *ws, size_t ws_bytes);
 
 /* Standard normals out[e], e < count, from Philox4x32-10 as described for
  * vip_ssvgd_step (device float [count]). */

@@ -1,0 +1,91 @@
+"""Tile-shape autotuner for the time-stepping kernel, with a JSON table.
+
+The blocked kernel comes in a few tile shapes (extended tile size, rows per
+thread, steps per launch); which one is fastest depends on the grid (how
+evenly the interior tiles cover it), the number of pairs and the device.
+`tune` times each candidate on the caller's own workload with HIP events on
+the current stream, keeps the fastest, and records it in a `TileTable` keyed
+by the grid and time length (or by the whole batch), saved as JSON so later
+runs reuse the measurement.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Callable, Iterable, Optional
+
+import torch
+
+from . import binding as vb
+
+
+def candidates(include_one_step: bool = True):
+    c = list(range(vb.lib().vip_tile_count()))
+    return ([-1] if include_one_step else []) + c
+
+
+def key_for(grid: vb.Grid, npairs: int) -> str:
+    return f"grid{grid.nx + 2 * grid.nb}x{grid.nz + 2 * grid.nb}:nt{grid.nt}:pairs{npairs}"
+
+
+def key_for_batch(problems) -> str:
+    return "batch:" + "|".join(key_for(p.grid, p.vel.shape[0] * p.geom.ns) for p in problems)
+
+
+class TileTable:
+    def __init__(self, path: Optional[str] = None):
+        self.path = path
+        self.entries = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.entries = json.load(f)
+
+    def get(self, key: str) -> Optional[int]:
+        e = self.entries.get(key)
+        return None if e is None else int(e["tile"])
+
+    def put(self, key: str, tile: int, timings_ms: dict):
+        self.entries[key] = {"tile": int(tile), "ms": {str(k): v for k, v in timings_ms.items()},
+                             "device": torch.cuda.get_device_name(0)}
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.entries, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def time_ms(fn: Callable[[], object], reps: int = 1) -> float:
+    fn()                                   # warm: first use may capture or allocate
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def tune(ctx: vb.Context, fn: Callable[[], object], key: str, table: Optional[TileTable] = None,
+         tiles: Optional[Iterable[int]] = None, reps: int = 1) -> int:
+    """Use the tabulated tile for `key`, or time `fn` under each candidate
+    tile, pick the fastest, record it; leaves the context set to it."""
+    if table is not None:
+        t = table.get(key)
+        if t is not None:
+            ctx.set_tile(t)
+            return t
+    timings = {}
+    for t in (candidates() if tiles is None else tiles):
+        ctx.set_tile(t)
+        try:
+            timings[t] = time_ms(fn, reps)
+        except vb.VipError as e:
+            if e.status != -7:                 # unsupported shape for this call: skip it
+                raise
+    best = min(timings, key=timings.get)
+    ctx.set_tile(best)
+    if table is not None:
+        table.put(key, best, timings)
+    return best

@@ -471,3 +471,106 @@ def workspace_view(ws: torch.Tensor, offset: int, count: int, dtype) -> torch.Te
     """A typed view into a workspace at a byte offset (for inspecting results)."""
     itemsize = torch.tensor([], dtype=dtype).element_size()
     return ws[offset: offset + count * itemsize].view(dtype)
+
+
+# ----------------------------------------------------------------------------
+# Batches of problems / ensembles
+# ----------------------------------------------------------------------------
+
+class VipProblem(ctypes.Structure):
+    _fields_ = [("grid", VipGrid), ("geom", VipGeometry), ("prior", VipPrior), ("np", ctypes.c_int32),
+                ("vel", ctypes.c_void_p), ("dobs", ctypes.c_void_p), ("sigma", ctypes.c_double),
+                ("logpost", ctypes.c_void_p), ("grad", ctypes.c_void_p)]
+
+
+class VipEnsemble(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int64), ("x", ctypes.c_void_p),
+                ("g", ctypes.c_void_p), ("eps", ctypes.c_double), ("prior", VipPrior),
+                ("xi", ctypes.c_void_p), ("h2_out", ctypes.c_void_p)]
+
+
+@dataclass
+class Problem:
+    """One inversion of a batch; logpost and grad are allocated when None."""
+    grid: Grid
+    geom: Geometry
+    vel: torch.Tensor
+    dobs: torch.Tensor
+    sigma: float
+    lo: Optional[torch.Tensor] = None
+    hi: Optional[torch.Tensor] = None
+    logpost: Optional[torch.Tensor] = None
+    grad: Optional[torch.Tensor] = None
+
+    def c(self) -> VipProblem:
+        if self.logpost is None:
+            self.logpost = torch.empty(self.vel.shape[0], dtype=torch.float64, device=self.vel.device)
+        if self.grad is None:
+            self.grad = torch.empty_like(self.vel)
+        pr = _prior(self.lo, self.hi) or VipPrior(VIP_PRIOR_NONE, None, None)
+        return VipProblem(self.grid.c(), self.geom.c(), pr, self.vel.shape[0],
+                          _ptr(self.vel, torch.float32), _ptr(self.dobs, torch.float32), self.sigma,
+                          _ptr(self.logpost, torch.float64), _ptr(self.grad, torch.float32))
+
+
+def _multi_lib():
+    L = lib()
+    vp, sz, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                  ctypes.c_int64, ctypes.c_uint64, ctypes.c_double)
+    PP, EP = ctypes.POINTER(VipProblem), ctypes.POINTER(VipEnsemble)
+    L.vip_grad_logpost_multi_workspace.argtypes = [i32, PP, i32, ctypes.POINTER(sz)]
+    L.vip_grad_logpost_multi.argtypes = [vp, i32, PP, i32, vp, sz]
+    L.vip_svgd_multi_workspace.argtypes = [i32, EP, ctypes.POINTER(sz)]
+    L.vip_svgd_step_multi.argtypes = [vp, i32, EP, i32, dbl, i32, vp, sz]
+    L.vip_ssvgd_step_multi.argtypes = [vp, i32, EP, i32, dbl, i32, u64, u64, vp, sz]
+    for f in (L.vip_grad_logpost_multi_workspace, L.vip_grad_logpost_multi,
+              L.vip_svgd_multi_workspace, L.vip_svgd_step_multi, L.vip_ssvgd_step_multi):
+        f.restype = ctypes.c_int
+    return L
+
+
+def vip_grad_logpost_multi(ctx: Context, problems, ckpt_every: int = 50, ws_tag: str = "multi"):
+    """Gradients of several inversions in merged launches; returns [(logpost, grad)]."""
+    ctx.sync_stream()
+    L = _multi_lib()
+    arr = (VipProblem * len(problems))(*[p.c() for p in problems])
+    nbytes = ctypes.c_size_t()
+    _check(L.vip_grad_logpost_multi_workspace(len(problems), arr, ckpt_every, ctypes.byref(nbytes)),
+           "vip_grad_logpost_multi_workspace")
+    ws = ctx.workspace(ws_tag, nbytes.value)
+    _check(L.vip_grad_logpost_multi(ctx.handle, len(problems), arr, ckpt_every,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel()),
+           "vip_grad_logpost_multi")
+    return [(p.logpost, p.grad) for p in problems]
+
+
+def _ensembles(xs, gs, eps, lo, hi, xis, h2s):
+    out = []
+    for k, (x, g) in enumerate(zip(xs, gs)):
+        n = x.shape[0]
+        pr = _prior(lo[k], hi[k]) if lo is not None else None
+        out.append(VipEnsemble(n, x.numel() // n, _ptr(x, torch.float32), _ptr(g, torch.float32),
+                               float(eps[k]), pr or VipPrior(VIP_PRIOR_NONE, None, None),
+                               _ptr(xis[k], torch.float32) if xis is not None else None,
+                               _ptr(h2s[k], torch.float64) if h2s is not None else None))
+    return (VipEnsemble * len(out))(*out)
+
+
+def vip_ssvgd_step_multi(ctx: Context, xs, gs, eps, xis=None, seed=0, stream=0, lo=None, hi=None,
+                         h2s=None, bw_mode=VIP_BW_MEDIAN_ALL, h_fixed=1.0,
+                         gram_prec=VIP_GRAM_BF16, noise=True, ws_tag="svgd_multi"):
+    """In-place (s)SVGD update of several independent ensembles; returns the workspace."""
+    ctx.sync_stream()
+    L = _multi_lib()
+    arr = _ensembles(xs, gs, eps, lo, hi, xis, h2s)
+    nbytes = ctypes.c_size_t()
+    _check(L.vip_svgd_multi_workspace(len(xs), arr, ctypes.byref(nbytes)), "vip_svgd_multi_workspace")
+    ws = ctx.workspace(ws_tag, nbytes.value)
+    if noise:
+        st = L.vip_ssvgd_step_multi(ctx.handle, len(xs), arr, bw_mode, h_fixed, gram_prec, seed,
+                                    stream, ctypes.c_void_p(ws.data_ptr()), ws.numel())
+    else:
+        st = L.vip_svgd_step_multi(ctx.handle, len(xs), arr, bw_mode, h_fixed, gram_prec,
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel())
+    _check(st, "vip_(s)svgd_step_multi")
+    return ws

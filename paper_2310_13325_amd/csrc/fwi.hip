@@ -378,16 +378,29 @@ int tile_count() { return kNumTiles; }
 // Default shape when no tuned choice exists: the fewest padded point-updates
 // per useful point-step (extended area / (covered interior x steps per launch),
 // with the waste of partial tiles counted).
+static double tile_cost(int c, int NX, int NZ) {
+  const TileCfg &t = kTiles[c];
+  const int ix = t.ex - 4 * t.tmax, iz = t.ez - 4 * t.tmax;
+  const double tiles = double((NX + ix - 1) / ix) * double((NZ + iz - 1) / iz);
+  const double work = tiles * t.ex * t.ez / (double(NX) * NZ);
+  const double traffic = (12.0 * work + 8.0) / t.tmax;
+  return std::max(work * 25.0 / 39.3, traffic / 5.0);   // VALU ops vs HBM bytes, per point-step
+}
+
 int default_tile(int NX, int NZ) {
+  int best = 0;
+  for (int c = 1; c < kNumTiles; ++c)
+    if (tile_cost(c, NX, NZ) < tile_cost(best, NX, NZ)) best = c;
+  return best;
+}
+
+// One shape for a batch of problems: the least total estimated cost.
+static int default_tile_multi(const std::vector<FwiDims> &Ds) {
   int best = 0;
   double best_cost = 1e300;
   for (int c = 0; c < kNumTiles; ++c) {
-    const TileCfg &t = kTiles[c];
-    const int ix = t.ex - 4 * t.tmax, iz = t.ez - 4 * t.tmax;
-    const double tiles = double((NX + ix - 1) / ix) * double((NZ + iz - 1) / iz);
-    const double work = tiles * t.ex * t.ez / (double(NX) * NZ);
-    const double traffic = (12.0 * tiles * t.ex * t.ez / (double(NX) * NZ) + 8.0) / t.tmax;
-    const double cost = std::max(work * 25.0 / 39.3, traffic / 5.0);   // VALU ops vs HBM bytes
+    double cost = 0.0;
+    for (const FwiDims &D : Ds) cost += tile_cost(c, D.NX, D.NZ) * double(D.N) * D.pairs * D.nt;
     if (cost < best_cost) {
       best_cost = cost;
       best = c;
@@ -396,7 +409,7 @@ int default_tile(int NX, int NZ) {
   return best;
 }
 
-static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, BlockArgs &a) {
+static vip_status set_tiles(int cfg, int npairs, BlockArgs &a) {
   const TileCfg &tc = kTiles[cfg];
   const int ix = tc.ex - 4 * tc.tmax, iz = tc.ez - 4 * tc.tmax;
   a.tiles_x = (a.NX + ix - 1) / ix;
@@ -404,6 +417,13 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
   const long long total = (long long)a.tiles_per_pair * npairs;
   if (total > (1LL << 30)) return VIP_E_UNSUPPORTED;
   a.total_tiles = int(total);
+  return VIP_OK;
+}
+
+static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, BlockArgs &a) {
+  const TileCfg &tc = kTiles[cfg];
+  VIP_TRY(set_tiles(cfg, npairs, a));
+  const long long total = a.total_tiles;
   const dim3 grid(unsigned((total + 7) / 8 * 8)), block(unsigned(tc.ex * (tc.ez / tc.rz)));
   hipStream_t s = ctx->s();
 #define VIP_BLOCK_CASE(C, EX, EZ, RZ, TM)                                              \
@@ -422,6 +442,58 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
 #undef VIP_BLOCK_CASE
   return VIP_E_UNSUPPORTED;
 }
+
+static vip_status launch_multi(vip_ctx *ctx, int cfg,
+                               const std::vector<const std::pair<int, BlockArgs> *> &items) {
+  MultiArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.nprob = int(items.size());
+  long long acc = 0;
+  for (int p = 0; p < m.nprob; ++p) {
+    m.start[p] = int(acc);
+    m.mode[p] = items[p]->first;
+    m.a[p] = items[p]->second;
+    acc += m.a[p].total_tiles;
+  }
+  if (acc > (1LL << 30)) return VIP_E_UNSUPPORTED;
+  m.start[m.nprob] = int(acc);
+  const TileCfg &tc = kTiles[cfg];
+  const dim3 grid(unsigned((acc + 7) / 8 * 8)), block(unsigned(tc.ex * (tc.ez / tc.rz)));
+  hipStream_t s = ctx->s();
+#define VIP_MULTI_CASE(C, EX, EZ, RZ, TM)                            \
+  if (cfg == C) {                                                    \
+    fd_block_multi<EX, EZ, RZ, TM><<<grid, block, 0, s>>>(m);        \
+    VIP_LAUNCH_CHECK();                                              \
+    return VIP_OK;                                                   \
+  }
+  VIP_MULTI_CASE(0, 112, 112, 14, 8)
+  VIP_MULTI_CASE(1, 80, 80, 10, 4)
+  VIP_MULTI_CASE(2, 96, 96, 12, 4)
+  VIP_MULTI_CASE(3, 64, 64, 8, 4)
+  VIP_MULTI_CASE(4, 128, 64, 8, 4)
+#undef VIP_MULTI_CASE
+  return VIP_E_UNSUPPORTED;
+}
+
+// Launches a blocked step, or records it (mode + arguments with the tile
+// geometry filled in) when several problems are merged into one launch.
+struct Emitter {
+  vip_ctx *ctx;
+  int cfg, npairs;
+  std::vector<std::pair<int, BlockArgs>> *list;
+  vip_status operator()(int mode, BlockArgs &a) const {
+    if (list) {
+      VIP_TRY(set_tiles(cfg, npairs, a));
+      list->emplace_back(mode, a);
+      return VIP_OK;
+    }
+    return launch_block(ctx, mode, cfg, npairs, a);
+  }
+  int timing_begin_(int kind) const { return list ? -1 : timing_begin(ctx, kind); }
+  void timing_end_(int run, int64_t launches, double pts) const {
+    if (!list) timing_end(ctx, run, launches, pts);
+  }
+};
 
 static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wavelet, int pair0) {
   BlockArgs a;
@@ -446,7 +518,7 @@ static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wav
   return a;
 }
 
-static vip_status forward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+static vip_status forward_sweep_blocked(const Emitter &emit, const FwiDims &D, const FwiPlan &P,
                                         const float *wavelet, int pair0, int npairs, float *data,
                                         float *ckpt) {
   const long long N = D.N;
@@ -455,7 +527,7 @@ static vip_status forward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const Fw
   const float *u_in = P.u[0], *q_in = P.q[0];
   long long in_stride = N;
   int buf = 0, launches = 0;
-  const int run = timing_begin(ctx, MODE_FWD);
+  const int run = emit.timing_begin_(MODE_FWD);
   for (int s = 0; s < D.nseg; ++s) {
     const int n0 = s * D.k, n1 = std::min(n0 + D.k, D.nt - 1);
     for (int n = n0; n < n1; n += tmax) {
@@ -480,18 +552,18 @@ static vip_status forward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const Fw
       }
       a.data = data;
       a.data_stride = (long long)D.nt * D.nr;
-      VIP_TRY(launch_block(ctx, BMODE_FWD, D.tile, npairs, a));
+      VIP_TRY(emit(BMODE_FWD, a));
       ++launches;
       u_in = a.u_out;
       q_in = a.q_out;
       in_stride = a.out_stride;
     }
   }
-  timing_end(ctx, run, launches, double(D.nt - 1) * double(N) * npairs);
+  emit.timing_end_(run, launches, double(D.nt - 1) * double(N) * npairs);
   return VIP_OK;
 }
 
-static vip_status backward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+static vip_status backward_sweep_blocked(const Emitter &emit, const FwiDims &D, const FwiPlan &P,
                                          const float *wavelet, int pair0, int npairs,
                                          const float *rho, const float *ckpt, double *acc64) {
   const long long N = D.N;
@@ -507,7 +579,7 @@ static vip_status backward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const F
     long long in_stride = s == 0 ? N : ck_stride;
     bool zero = s == 0;
     int buf = 0, launches = 0;
-    const int run_rec = timing_begin(ctx, MODE_REC);
+    const int run_rec = emit.timing_begin_(MODE_REC);
     for (int n = n0; n < n1; n += tmax) {
       const int T = std::min(tmax, n1 - n);
       BlockArgs a = block_args(D, P, wavelet, pair0);
@@ -526,16 +598,16 @@ static vip_status backward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const F
       }
       a.seg = P.seg;
       a.seg_stride = seg_stride;
-      VIP_TRY(launch_block(ctx, BMODE_REC, D.tile, npairs, a));
+      VIP_TRY(emit(BMODE_REC, a));
       ++launches;
       u_in = a.u_out;
       q_in = a.q_out;
       in_stride = N;
       zero = false;
     }
-    timing_end(ctx, run_rec, launches, double(n1 - n0) * double(N) * npairs);
+    emit.timing_end_(run_rec, launches, double(n1 - n0) * double(N) * npairs);
     launches = 0;
-    const int run_adj = timing_begin(ctx, MODE_ADJ);
+    const int run_adj = emit.timing_begin_(MODE_ADJ);
     for (int n = n1 - 1; n >= n0; n -= tmax) {
       const int T = std::min(tmax, n - n0 + 1);
       BlockArgs a = block_args(D, P, wavelet, pair0);
@@ -556,11 +628,11 @@ static vip_status backward_sweep_blocked(vip_ctx *ctx, const FwiDims &D, const F
       a.seg_stride = seg_stride;
       a.acc64 = acc64;
       a.acc64_stride = N;
-      VIP_TRY(launch_block(ctx, BMODE_ADJ, D.tile, npairs, a));
+      VIP_TRY(emit(BMODE_ADJ, a));
       ++launches;
       adj_zero = false;
     }
-    timing_end(ctx, run_adj, launches, double(n1 - n0) * double(N) * npairs);
+    emit.timing_end_(run_adj, launches, double(n1 - n0) * double(N) * npairs);
   }
   return VIP_OK;
 }
@@ -680,14 +752,16 @@ static vip_status backward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const Fw
 vip_status forward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
                          int pair0, int npairs, float *data, float *ckpt) {
   if (D.tile < 0) return forward_sweep_stream(ctx, D, P, wavelet, pair0, npairs, data, ckpt);
-  return forward_sweep_blocked(ctx, D, P, wavelet, pair0, npairs, data, ckpt);
+  const Emitter emit{ctx, D.tile, npairs, nullptr};
+  return forward_sweep_blocked(emit, D, P, wavelet, pair0, npairs, data, ckpt);
 }
 
 vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *wavelet,
                           int pair0, int npairs, const float *rho, const float *ckpt,
                           double *acc64) {
   if (D.tile < 0) return backward_sweep_stream(ctx, D, P, wavelet, pair0, npairs, rho, ckpt, acc64);
-  return backward_sweep_blocked(ctx, D, P, wavelet, pair0, npairs, rho, ckpt, acc64);
+  const Emitter emit{ctx, D.tile, npairs, nullptr};
+  return backward_sweep_blocked(emit, D, P, wavelet, pair0, npairs, rho, ckpt, acc64);
 }
 
 vip_status launch_residual(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, int pair0,
@@ -718,6 +792,44 @@ vip_status launch_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, cons
   logpost_kernel<<<dim3(D.np), dim3(256), 0, ctx->s()>>>(P.J, vel, lo, hi, D.ns,
                                                          (long long)D.nx * D.nz, logpost, P.status);
   VIP_LAUNCH_CHECK();
+  return VIP_OK;
+}
+
+
+// ---- batches of problems ------------------------------------------------------
+
+static vip_status multi_dims(int32_t nprob, const vip_problem *probs, int32_t k, bool need_wavelet,
+                             std::vector<FwiDims> *Ds) {
+  if (nprob < 1 || nprob > VIP_MAX_BATCH || !probs) return VIP_E_ARG;
+  Ds->resize(size_t(nprob));
+  for (int p = 0; p < nprob; ++p)
+    VIP_TRY(make_dims(&probs[p].grid, &probs[p].geom, probs[p].np, k, 0, need_wavelet, &(*Ds)[size_t(p)]));
+  return VIP_OK;
+}
+
+// Sub-workspaces of the problems, one after the other; one status word for all.
+static size_t plan_multi(const std::vector<FwiDims> &Ds, char *base, std::vector<FwiPlan> *Ps) {
+  size_t off = kStatusBytes;
+  Ps->resize(Ds.size());
+  for (size_t p = 0; p < Ds.size(); ++p) {
+    FwiPlan &P = (*Ps)[p];
+    plan_fwi(Ds[p], base ? base + off : nullptr, PLAN_GRAD, &P);
+    P.status = reinterpret_cast<uint32_t *>(base);
+    off = align_up(off + P.bytes);
+  }
+  return off;
+}
+
+static vip_status launch_merged(vip_ctx *ctx, int cfg,
+                                const std::vector<std::vector<std::pair<int, BlockArgs>>> &lists) {
+  size_t longest = 0;
+  for (auto &l : lists) longest = std::max(longest, l.size());
+  for (size_t i = 0; i < longest; ++i) {
+    std::vector<const std::pair<int, BlockArgs> *> items;
+    for (auto &l : lists)
+      if (i < l.size()) items.push_back(&l[i]);
+    VIP_TRY(launch_multi(ctx, cfg, items));
+  }
   return VIP_OK;
 }
 
@@ -879,6 +991,72 @@ vip_status vip_adjoint_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
   VIP_TRY(backward_sweep(ctx, D, P, geom->wavelet, 0, int(D.pairs), grad_data,
                          static_cast<const float *>(tape), P.acc64));
   return launch_finalize(ctx, D, P, vel, grad_vel, 1.0f);
+}
+
+vip_status vip_grad_logpost_multi_workspace(int32_t nprob, const vip_problem *probs,
+                                            int32_t ckpt_every, size_t *bytes) {
+  if (!bytes) return VIP_E_ARG;
+  std::vector<FwiDims> Ds;
+  VIP_TRY(multi_dims(nprob, probs, ckpt_every, false, &Ds));
+  std::vector<FwiPlan> Ps;
+  *bytes = plan_multi(Ds, nullptr, &Ps);
+  return VIP_OK;
+}
+
+vip_status vip_grad_logpost_multi(vip_ctx *ctx, int32_t nprob, const vip_problem *probs,
+                                  int32_t ckpt_every, void *ws, size_t ws_bytes) {
+  if (!ctx || !ws) return VIP_E_ARG;
+  std::vector<FwiDims> Ds;
+  VIP_TRY(multi_dims(nprob, probs, ckpt_every, true, &Ds));
+  for (int p = 0; p < nprob; ++p) {
+    const vip_problem &q = probs[p];
+    if (!q.vel || !q.dobs || !q.logpost || !q.grad) return VIP_E_ARG;
+    if (!(q.sigma > 0.0) || !std::isfinite(q.sigma)) return VIP_E_ARG;
+    if (q.prior.kind != VIP_PRIOR_NONE &&
+        (q.prior.kind != VIP_PRIOR_UNIFORM_CLIP || !q.prior.lo || !q.prior.hi))
+      return VIP_E_ARG;
+  }
+  const int cfg = ctx->tile >= 0 ? ctx->tile : default_tile_multi(Ds);
+  if (ctx->tile == -1) return VIP_E_UNSUPPORTED;   // batching needs a blocked tile shape
+  for (FwiDims &D : Ds) D.tile = cfg;
+  std::vector<FwiPlan> Ps;
+  const size_t need = plan_multi(Ds, static_cast<char *>(ws), &Ps);
+  if (ws_bytes < need || !aligned(ws)) return VIP_E_WORKSPACE;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  KeyBuilder kb;
+  kb.add(std::string("multi")).add(cfg).add(nprob).add(ckpt_every).add(ws);
+  for (int p = 0; p < nprob; ++p) {
+    const vip_problem &q = probs[p];
+    kb.add(q.grid).add(q.np).add(q.vel).add(q.dobs).add(q.sigma).add(q.logpost).add(q.grad)
+        .add(q.prior.kind).add(q.prior.lo).add(q.prior.hi).add(q.geom.wavelet).add(q.geom.ns)
+        .add(q.geom.nr);
+    kb.add_array(q.geom.src_ix, q.geom.ns).add_array(q.geom.src_iz, q.geom.ns)
+        .add_array(q.geom.rec_ix, q.geom.nr).add_array(q.geom.rec_iz, q.geom.nr);
+  }
+  return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
+    std::vector<std::vector<std::pair<int, BlockArgs>>> fwd(nprob), bwd(nprob);
+    for (int p = 0; p < nprob; ++p) {
+      const FwiDims &D = Ds[p];
+      const FwiPlan &P = Ps[p];
+      VIP_TRY(upload_tables(ctx, D, &probs[p].grid, &probs[p].geom, P));
+      VIP_TRY(launch_coeff(ctx, D, &probs[p].grid, probs[p].vel, P));
+      VIP_TRY(fill_f64(ctx->s(), P.acc64, size_t(D.pairs * D.N), 0.0));
+      const Emitter ef{ctx, cfg, int(D.pairs), &fwd[p]};
+      VIP_TRY(forward_sweep_blocked(ef, D, P, probs[p].geom.wavelet, 0, int(D.pairs), P.resid, P.ckpt));
+      const Emitter eb{ctx, cfg, int(D.pairs), &bwd[p]};
+      VIP_TRY(backward_sweep_blocked(eb, D, P, probs[p].geom.wavelet, 0, int(D.pairs), P.resid,
+                                     P.ckpt, P.acc64));
+    }
+    VIP_TRY(launch_merged(ctx, cfg, fwd));
+    for (int p = 0; p < nprob; ++p)
+      VIP_TRY(launch_residual(ctx, Ds[p], Ps[p], 0, int(Ds[p].pairs), probs[p].dobs, probs[p].sigma));
+    VIP_TRY(launch_merged(ctx, cfg, bwd));
+    for (int p = 0; p < nprob; ++p) {
+      VIP_TRY(launch_finalize(ctx, Ds[p], Ps[p], probs[p].vel, probs[p].grad, -1.0f));
+      VIP_TRY(launch_logpost(ctx, Ds[p], Ps[p], probs[p].vel, &probs[p].prior, probs[p].logpost));
+    }
+    return VIP_OK;
+  });
 }
 
 }  // extern "C"

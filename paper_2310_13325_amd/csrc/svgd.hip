@@ -450,7 +450,8 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
 static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
                               double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
                               const vip_prior *prior, bool noise, const float *xi, uint64_t seed,
-                              uint64_t stream, double *h2_out, void *ws, size_t ws_bytes) {
+                              uint64_t stream, double *h2_out, void *ws, size_t ws_bytes,
+                              uint32_t *status_ptr = nullptr) {
   if (!ctx || !x || !g || !ws) return VIP_E_ARG;
   if (n < 1 || d < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return VIP_E_ARG;
   if (bw_mode < VIP_BW_MEDIAN_ALL || bw_mode > VIP_BW_FIXED) return VIP_E_ARG;
@@ -466,6 +467,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   SvgdPlan P;
   plan_svgd(n, d, static_cast<char *>(ws), &P);
   if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
+  if (status_ptr) P.status = status_ptr;
   VIP_TRY_HIP(hipSetDevice(ctx->device));
   ctx->active = ctx->user;
   hipStream_t s = ctx->user;
@@ -569,6 +571,66 @@ vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const flo
                          const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes) {
   return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr, 0, 0,
                      h2_out, ws, ws_bytes);
+}
+
+}  // extern "C"
+
+namespace vip {
+
+static size_t plan_svgd_multi(int32_t nens, const vip_ensemble *ens, std::vector<size_t> *offs) {
+  size_t off = kStatusBytes;
+  offs->clear();
+  for (int e = 0; e < nens; ++e) {
+    SvgdPlan P;
+    plan_svgd(ens[e].n, ens[e].d, nullptr, &P);
+    offs->push_back(off);
+    off = align_up(off + P.bytes);
+  }
+  return off;
+}
+
+static vip_status svgd_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *ens, int32_t bw_mode,
+                             double h_fixed, int32_t gram_prec, bool noise, uint64_t seed,
+                             uint64_t stream, void *ws, size_t ws_bytes) {
+  if (!ctx || !ens || !ws || nens < 1) return VIP_E_ARG;
+  for (int e = 0; e < nens; ++e)
+    if (ens[e].n < 1 || ens[e].d < 1) return VIP_E_ARG;
+  std::vector<size_t> offs;
+  const size_t need = plan_svgd_multi(nens, ens, &offs);
+  if (ws_bytes < need || !aligned(ws)) return VIP_E_WORKSPACE;
+  char *base = static_cast<char *>(ws);
+  for (int e = 0; e < nens; ++e) {
+    const vip_ensemble &E = ens[e];
+    VIP_TRY(svgd_common(ctx, E.n, E.d, E.x, E.g, E.eps, bw_mode, h_fixed, gram_prec, &E.prior, noise,
+                        E.xi, seed, stream + uint64_t(e), E.h2_out, base + offs[size_t(e)],
+                        ws_bytes - offs[size_t(e)], reinterpret_cast<uint32_t *>(base)));
+  }
+  return VIP_OK;
+}
+
+}  // namespace vip
+
+extern "C" {
+
+vip_status vip_svgd_multi_workspace(int32_t nens, const vip_ensemble *ens, size_t *bytes) {
+  if (!bytes || !ens || nens < 1) return VIP_E_ARG;
+  for (int e = 0; e < nens; ++e)
+    if (ens[e].n < 1 || ens[e].d < 1) return VIP_E_ARG;
+  std::vector<size_t> offs;
+  *bytes = vip::plan_svgd_multi(nens, ens, &offs);
+  return VIP_OK;
+}
+
+vip_status vip_svgd_step_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *ens, int32_t bw_mode,
+                               double h_fixed, int32_t gram_prec, void *ws, size_t ws_bytes) {
+  return vip::svgd_multi(ctx, nens, ens, bw_mode, h_fixed, gram_prec, false, 0, 0, ws, ws_bytes);
+}
+
+vip_status vip_ssvgd_step_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *ens,
+                                int32_t bw_mode, double h_fixed, int32_t gram_prec, uint64_t seed,
+                                uint64_t stream, void *ws, size_t ws_bytes) {
+  return vip::svgd_multi(ctx, nens, ens, bw_mode, h_fixed, gram_prec, true, seed, stream, ws,
+                         ws_bytes);
 }
 
 vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
