@@ -35,13 +35,24 @@ if ROOT not in sys.path:
 
 METRIC = "particle gradients/s (fwd+adjoint) + SVGD steps/s vs plain path, at stated err"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per padded grid point per pair per launch of the
-# time-stepping kernel: read u, q, c and write u, q (20 B); the recompute also
-# writes L u + f (4 B); the adjoint also reads it (4 B) and updates the FP32
-# segment imaging sum (8 B).
-BYTES_PER_POINT_STEP = {"forward": 20.0, "recompute": 24.0, "adjoint": 32.0}
-COUNTERS = os.path.join(ROOT, "profiles", "fd_step_c2_counters.json")
-STEP_SOURCE = os.path.join(ROOT, "paper_2310_13325_amd", "csrc", "fwi.hip")
+# FP32 vector peak without packed (dual) FP32 instructions, which the build
+# disables: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+ALU_PUBLISHED_TFLOPS = 157.3
+# Algorithmic HBM bytes per padded grid point per pair per time step (a
+# "point-step"), the per-unit figures of a streaming sweep in the increment
+# form: read u, q, c and write u, q (20 B); the recompute also stores
+# a^n = L u^n + f^n (4 B), the adjoint reads it back (4 B).  Over the three
+# sweeps this is 68 B per point-step and shot.
+BYTES_PER_POINT_STEP = {"forward": 20.0, "recompute": 24.0, "adjoint": 24.0}
+# Algorithmic flops per point-step: the fourth-order Laplacian with symmetric
+# weights (4 pair sums, 1 centre product, 4 fused multiply-adds = 13), the
+# increment update q' = g (q + c L u), u' = g u + q' (5); the adjoint adds the
+# imaging product-sum z a (2).
+FLOPS_PER_POINT_STEP = {"forward": 18.0, "recompute": 18.0, "adjoint": 20.0}
+COUNTERS = os.path.join(ROOT, "profiles", "fd_block_c2_counters.json")
+STEP_SOURCES = [os.path.join(ROOT, "paper_2310_13325_amd", "csrc", f)
+                for f in ("fwi.hip", "fd_block.h", "fd_block_body.inc")]
 
 
 def log(msg):
@@ -49,8 +60,12 @@ def log(msg):
 
 
 def source_hash() -> str:
-    with open(STEP_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the time-stepping kernel's sources (counters go stale with them)."""
+    h = hashlib.sha256()
+    for path in STEP_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_counters():
@@ -193,13 +208,22 @@ def main():
         raise RuntimeError("non-finite particles after the timed steps")
 
     value = args.steps * n / elapsed
+    tile = ctx.tile_for(S["grid"])
+    if tile >= 0:
+        sh = vb.tile_shape(tile)
+        kname = (f"fd_block (temporally blocked, {sh['ex']}x{sh['ez']} extended tile, "
+                 f"up to {sh['tmax']} steps per launch)")
+    else:
+        kname = "fd_step (one step per launch)"
     kinds = {}
     for k, t in timing.items():
         if t["launches"]:
-            per_launch_ms = t["ms"] / t["launches"]
-            bytes_per_launch = BYTES_PER_POINT_STEP[k] * t["point_steps"] / t["launches"]
-            kinds[k] = {"launches": t["launches"], "avg_launch_us": round(per_launch_ms * 1e3, 2),
-                        "alg_GBps": round(bytes_per_launch / (per_launch_ms * 1e-3) / 1e9, 1),
+            per_launch_s = t["ms"] * 1e-3 / t["launches"]
+            ps = t["point_steps"] / t["launches"]
+            kinds[k] = {"launches": t["launches"], "avg_launch_us": round(per_launch_s * 1e6, 2),
+                        "point_steps_per_launch": ps,
+                        "alg_GBps": round(BYTES_PER_POINT_STEP[k] * ps / per_launch_s / 1e9, 1),
+                        "alg_TFLOPs": round(FLOPS_PER_POINT_STEP[k] * ps / per_launch_s / 1e12, 3),
                         "share_of_step": round(t["ms"] / 1e3 / elapsed, 3)}
     dom = max(kinds, key=lambda k: kinds[k]["share_of_step"])
     ach = kinds[dom]["alg_GBps"]
@@ -207,7 +231,14 @@ def main():
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else traffic.get(dom),
-                "kernel": f"fd_step ({dom} mode)", "modes": kinds}
+                "kernel": f"{kname}, {dom} mode", "modes": kinds,
+                "alu": {"achieved": kinds[dom]["alg_TFLOPs"], "peak": ALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s",
+                        "frac": round(kinds[dom]["alg_TFLOPs"] / ALU_PEAK_TFLOPS, 4),
+                        "frac_of_published": round(kinds[dom]["alg_TFLOPs"] / ALU_PUBLISHED_TFLOPS, 4)},
+                "gradient_ceiling_pg_per_s": round(
+                    HBM_PEAK_GBS * 1e9 / (sum(BYTES_PER_POINT_STEP.values()) * prob.ns * prob.nt
+                                          * (prob.nx + 2 * prob.nb) * (prob.nz + 2 * prob.nb)), 1)}
 
     extra = {}
     if not args.no_plain:

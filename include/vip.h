@@ -127,6 +127,13 @@ vip_status vip_set_graph_mode(vip_ctx *ctx, int enable);
  * on chip. */
 vip_status vip_set_tile(vip_ctx *ctx, int tile);
 int vip_tile_count(void);
+/* Shape of blocked tile `tile`: shape[0..3] = extended width, extended height
+ * (grid points, interior plus a halo of 2 points per step on each side), rows
+ * per thread, steps per launch.  VIP_E_ARG for an index out of range. */
+vip_status vip_tile_shape(int tile, int32_t shape[4]);
+/* The shape a single-problem call on `grid` would use with this context's
+ * setting: -1 (one step per launch) or a blocked tile index. */
+vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int32_t *tile);
 /* Human-readable name of a status code (static string). */
 const char *vip_status_string(int status);
 /* Library version, major*10000 + minor*100 + patch. */

@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
             "vip_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "vip_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
             "vip_tile_count": (ctypes.c_int, []),
+            "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+            "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
         }
         for name, (res, args) in sig.items():
@@ -139,6 +141,13 @@ def status_string(s: int) -> str:
 def _check(status: int, where: str):
     if status != VIP_OK:
         raise VipError(status, where)
+
+
+def tile_shape(tile: int) -> dict:
+    """Extended width/height, rows per thread and steps per launch of a blocked tile."""
+    a = (ctypes.c_int32 * 4)()
+    _check(lib().vip_tile_shape(int(tile), a), "vip_tile_shape")
+    return {"ex": a[0], "ez": a[1], "rz": a[2], "tmax": a[3]}
 
 
 # ----------------------------------------------------------------------------
@@ -258,6 +267,14 @@ class Context:
     def set_tile(self, tile: int):
         """-2 automatic, -1 one step per launch, 0.. a temporally blocked shape."""
         _check(lib().vip_set_tile(self._h, int(tile)), "vip_set_tile")
+
+    def tile_for(self, grid: "Grid") -> int:
+        """Tile index a single-problem call on `grid` uses (-1: one step per launch)."""
+        t = ctypes.c_int32(0)
+        g = grid.c()
+        _check(lib().vip_tile_for_grid(self._h, ctypes.byref(g), ctypes.byref(t)),
+               "vip_tile_for_grid")
+        return int(t.value)
 
     def set_timing(self, on: bool):
         _check(lib().vip_set_timing(self._h, 1 if on else 0), "vip_set_timing")

@@ -847,6 +847,25 @@ vip_status vip_set_tile(vip_ctx *ctx, int tile) {
   return VIP_OK;
 }
 
+vip_status vip_tile_shape(int tile, int32_t shape[4]) {
+  if (!shape || tile < 0 || tile >= tile_count()) return VIP_E_ARG;
+  shape[0] = kTiles[tile].ex;
+  shape[1] = kTiles[tile].ez;
+  shape[2] = kTiles[tile].rz;
+  shape[3] = kTiles[tile].tmax;
+  return VIP_OK;
+}
+
+vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int32_t *tile) {
+  if (!ctx || !grid || !tile || grid->nx <= 0 || grid->nz <= 0 || grid->nb < 0) return VIP_E_ARG;
+  if (ctx->tile >= -1) {
+    *tile = ctx->tile;
+  } else {
+    *tile = default_tile(grid->nx + 2 * grid->nb, grid->nz + 2 * grid->nb);
+  }
+  return VIP_OK;
+}
+
 vip_status vip_forward_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
                                  size_t *bytes) {
   if (!bytes) return VIP_E_ARG;
