@@ -124,7 +124,8 @@ vip_status vip_set_graph_mode(vip_ctx *ctx, int enable);
  * grid; -1 advances one step per launch (each block a 64 x 4*rz tile with its
  * halo staged in LDS); 0 .. vip_tile_count()-1 select a temporally blocked
  * shape that advances up to 4 or 8 steps per launch on an extended tile kept
- * on chip. */
+ * on chip.  Padded grids of 2^29 points or more always use one step per
+ * launch (a blocked shape then gives VIP_E_UNSUPPORTED). */
 vip_status vip_set_tile(vip_ctx *ctx, int tile);
 int vip_tile_count(void);
 /* Shape of blocked tile `tile`: shape[0..3] = extended width, extended height

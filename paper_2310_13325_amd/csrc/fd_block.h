@@ -11,19 +11,23 @@
 // (e = EX EZ / (IX IZ)) instead of 20.
 //
 // Thread layout: thread t owns column t % EX of the extended tile and the RZ
-// consecutive rows of strip t / EX, keeping u, q, c and the damping of those
-// points in registers.  Per step the current u of every point is published in
-// a double-buffered LDS tile (two zero cells of padding on each side); a
-// thread reads its x-neighbours and the two rows beyond each end of its strip
-// from LDS and the rows inside its strip from registers.  One barrier per
-// step.
+// consecutive rows of strip t / EX, keeping u, q and (forward, recompute) c of
+// those points in registers.  Per step the current u of every point is
+// published in a double-buffered LDS tile (two zero cells of padding on each
+// side); a thread reads its x-neighbours and the two rows beyond each end of
+// its strip from LDS and the rows inside its strip from registers.  One
+// barrier per step.  The adjoint keeps c in LDS instead and its FP32 imaging
+// sum and the prefetched aⁿ of the next step in registers.
 //
 // Points outside the padded grid have g = c = 0, so they stay exactly 0 (the
 // zero ghost layers of the scheme).  The source (forward, recompute) and the
-// residual (adjoint) are injected at every point of the extended tile that
+// residual (adjoint) are added to q at every point of the extended tile that
 // carries one, so halo points evolve exactly like the owner's; receiver
 // traces, the aⁿ segment stores and loads, and the imaging sum are handled for
 // owned points only.
+//
+// Field loads go through buffer descriptors whose range check returns 0 for
+// rows above or below the grid, so a strip needs no per-row bounds test.
 #pragma once
 
 #include "fwi_plan.h"
@@ -32,6 +36,22 @@ namespace vip {
 
 enum { BMODE_FWD = 0, BMODE_REC = 1, BMODE_ADJ = 2 };
 
+// Raw buffer descriptor over one [N] float field (stride 0, N * 4 bytes, the
+// gfx9-family data-format word).  Offsets are bytes in the VGPR offset, which
+// the hardware checks against the size: loads out of range return 0 and
+// stores out of range are dropped.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ BufRsrc field_rsrc(const float *base, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, n * 4, 0x00020000);
+}
+// (The b32 builtins move raw 32-bit words, hence the bit casts.)
+__device__ __forceinline__ float field_load(BufRsrc r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, 0));
+}
+__device__ __forceinline__ void field_store(BufRsrc r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(off), 0, 0);
+}
+
 struct BlockArgs {
   int NX, NZ, N;
   int tiles_x, tiles_per_pair, total_tiles;
@@ -39,7 +59,8 @@ struct BlockArgs {
   int steps;              // T <= TMAX
   int n_start;            // FWD/REC: first input time index; ADJ: first n (produces z^{n+1}), descending
   int seg_n0;             // REC/ADJ: time index of segment slot 0
-  float cx, cz, inv_area;
+  float w1x, w2x, w1z, w2z;   // Laplacian weights 4/3, -1/12 times 1/dx^2 (x) or 1/dz^2 (z)
+  float inv_area;
   const float *gx, *gz, *c;
   const int *src_idx, *rrow, *rmap;
   const float *wavelet;
@@ -58,21 +79,16 @@ struct BlockArgs {
   long long acc64_stride;
 };
 
-// LDS of one block, per mode.  The adjoint keeps one u buffer (two barriers
-// per step) and c and the imaging sum in LDS, which leaves registers for
-// prefetching the next step's aⁿ; forward and recompute double-buffer u and
-// keep c in registers.
+// LDS of one block, per mode: double-buffered u; the adjoint also keeps c.
 template <int MODE, int EX, int EZ, int TMAX>
 struct BlockLds {
   static constexpr bool ADJ = MODE == BMODE_ADJ;
-  static constexpr int NBUF = ADJ ? 1 : 2;
   static constexpr int LW = EX + 4;           // 2 zero cells each side
-  float u[NBUF][EZ + 4][LW];
+  float u[2][EZ + 4][LW];
   float gz[EZ];                               // z damping per tile row (0 off the grid)
   int rr[EZ];                                 // receiver-row index per tile row (-1: none)
   float inj[TMAX];                            // forward / recompute: w(t_n)/(dx dz) per step
   float c[ADJ ? EZ : 1][ADJ ? EX : 1];        // adjoint: c per point
-  float acc[ADJ ? EZ : 1][ADJ ? EX : 1];      // adjoint: FP32 imaging sum of the launch
 };
 
 template <int EX, int EZ, int TMAX>
@@ -96,16 +112,13 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_block(BlockArgs a) {
   constexpr int H = 2 * TMAX;                 // halo width
   constexpr int IX = EX - 2 * H, IZ = EZ - 2 * H;
   constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
-  constexpr float w1 = 4.0f / 3.0f, w2 = -1.0f / 12.0f;
   constexpr bool ADJ = MODE == BMODE_ADJ;
-  constexpr int NBUF = ADJ ? 1 : 2;
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
-  __shared__ float lds[NBUF][EZ + 4][LW];
+  __shared__ float lds[2][EZ + 4][LW];
   __shared__ float gzs[EZ];     // z damping of each extended-tile row (0 outside the grid)
   __shared__ int rrs[EZ];       // receiver-row index of each extended-tile row (-1: none)
   __shared__ float injs[TMAX];  // forward / recompute: source term w(t_n)/(dx dz) of each step
   __shared__ float cs[ADJ ? EZ : 1][ADJ ? EX : 1];     // adjoint: c of each point
-  __shared__ float accs[ADJ ? EZ : 1][ADJ ? EX : 1];   // adjoint: FP32 imaging sum of this launch
   const int t = xcd_tile();
   if (t >= a.total_tiles) return;
 #include "fd_block_body.inc"
@@ -118,16 +131,13 @@ __device__ __forceinline__ void fd_block_multi_body(const BlockArgs &a, const in
   constexpr int H = 2 * TMAX;                 // halo width
   constexpr int IX = EX - 2 * H, IZ = EZ - 2 * H;
   constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
-  constexpr float w1 = 4.0f / 3.0f, w2 = -1.0f / 12.0f;
   constexpr bool ADJ = MODE == BMODE_ADJ;
-  constexpr int NBUF = ADJ ? 1 : 2;
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
   auto &lds = sh.u;
   auto &gzs = sh.gz;
   auto &rrs = sh.rr;
   auto &injs = sh.inj;
   auto &cs = sh.c;
-  auto &accs = sh.acc;
 #include "fd_block_body.inc"
 }
 

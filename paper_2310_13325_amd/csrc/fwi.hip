@@ -411,6 +411,8 @@ static int default_tile_multi(const std::vector<FwiDims> &Ds) {
 
 static vip_status set_tiles(int cfg, int npairs, BlockArgs &a) {
   const TileCfg &tc = kTiles[cfg];
+  // byte offsets into one field (4 N) must stay below 2^31 (see field_rsrc)
+  if (a.N >= kMaxBlockedPoints) return VIP_E_UNSUPPORTED;
   const int ix = tc.ex - 4 * tc.tmax, iz = tc.ez - 4 * tc.tmax;
   a.tiles_x = (a.NX + ix - 1) / ix;
   a.tiles_per_pair = a.tiles_x * ((a.NZ + iz - 1) / iz);
@@ -505,8 +507,10 @@ static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wav
   a.ns = D.ns;
   a.nt = D.nt;
   a.nr = D.nr;
-  a.cx = D.cx;
-  a.cz = D.cz;
+  a.w1x = float(4.0 / 3.0 * D.inv_dx2);
+  a.w2x = float(-1.0 / 12.0 * D.inv_dx2);
+  a.w1z = float(4.0 / 3.0 * D.inv_dz2);
+  a.w2z = float(-1.0 / 12.0 * D.inv_dz2);
   a.inv_area = D.inv_area;
   a.gx = P.gx;
   a.gz = P.gz;
@@ -861,7 +865,8 @@ vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int32_t *
   if (ctx->tile >= -1) {
     *tile = ctx->tile;
   } else {
-    *tile = default_tile(grid->nx + 2 * grid->nb, grid->nz + 2 * grid->nb);
+    const int NX = grid->nx + 2 * grid->nb, NZ = grid->nz + 2 * grid->nb;
+    *tile = (long long)NX * NZ < kMaxBlockedPoints ? default_tile(NX, NZ) : -1;
   }
   return VIP_OK;
 }

@@ -21,6 +21,7 @@ struct FwiDims {
   int rz;               // rows per thread in the streaming step kernel (tile height 4*rz)
   int tile;             // temporally blocked tile shape, -1 = one step per launch
   float cx, cz, inv_area;
+  double inv_dx2, inv_dz2;   // 1/dx^2, 1/dz^2 before rounding
 };
 
 // Stability of the fourth-order / leapfrog scheme: the largest eigenvalue of
@@ -31,6 +32,8 @@ inline double courant_factor(const vip_grid &g) {
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Largest padded grid (points) the temporally blocked kernel accepts.
+constexpr long long kMaxBlockedPoints = 1LL << 29;
 int default_tile(int NX, int NZ);   // fwi.hip
 int tile_count();
 
@@ -87,7 +90,9 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
     d.nrows = int(std::unique(rows.begin(), rows.end()) - rows.begin());
   }
   d.rz = default_rz(d.NZ);
-  d.tile = default_tile(d.NX, d.NZ);
+  d.tile = d.N < kMaxBlockedPoints ? default_tile(d.NX, d.NZ) : -1;
+  d.inv_dx2 = 1.0 / (double(g.dx) * g.dx);
+  d.inv_dz2 = 1.0 / (double(g.dz) * g.dz);
   d.cx = float(1.0 / (g.dx * g.dx));
   d.cz = float(1.0 / (g.dz * g.dz));
   d.inv_area = float(1.0 / (g.dx * g.dz));

@@ -1,6 +1,8 @@
 """The plain per-pair GPU path computes the same gradient as the batched path
-(same scheme, same FP32 arithmetic forms, imaging summed in FP64 directly
-instead of per checkpoint segment) and matches the FP64 oracle."""
+(same scheme in FP32; the plain path sums the Laplacian in the difference form
+and the imaging term in FP64 directly, the batched path takes each symmetric
+pair against 2u and sums the imaging term per checkpoint segment) and both
+match the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -27,4 +29,7 @@ def test_plain_path_matches_oracle_and_batched_path():
         assert rel(g_p[p], g_ref[p]) <= 1e-4
         assert rel(g_p[p], g_b[p]) <= 1e-5
     assert np.allclose(lp_p.cpu().numpy(), lp_ref, rtol=1e-5, atol=0)
-    assert np.allclose(lp_p.cpu().numpy(), lp_b.cpu().numpy(), rtol=1e-7, atol=0)
+    assert np.allclose(lp_b.cpu().numpy(), lp_ref, rtol=1e-5, atol=0)
+    # Two FP32 roundings of the same misfit: each is within the data error of
+    # the oracle (|dJ|/J <= 2 |dd|/|r|, about 1e-6 here), so they agree to 1e-6.
+    assert np.allclose(lp_p.cpu().numpy(), lp_b.cpu().numpy(), rtol=1e-6, atol=0)
