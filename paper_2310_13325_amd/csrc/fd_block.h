@@ -75,8 +75,11 @@ struct BlockArgs {
   long long seg_stride;
   const float *rho;       // ADJ: residual [pair][nt][nr]
   long long rho_stride;
-  double *acc64;          // ADJ: imaging sum [pair][N] (+= per launch)
+  float *acc32;           // ADJ: FP32 imaging sum within a checkpoint segment [pair][N]
+  double *acc64;          // ADJ: FP64 imaging sum across segments [pair][N]
   long long acc64_stride;
+  int acc_first;          // ADJ: first launch of the segment (acc32 not read)
+  int acc_flush;          // ADJ: last launch of the segment (adds into acc64, acc32 not written)
 };
 
 // LDS of one block, per mode: double-buffered u; the adjoint also keeps c.
@@ -106,15 +109,42 @@ __device__ __forceinline__ int xcd_tile() {
   return (b & 7) * per + (b >> 3);
 }
 
+// LDS bytes of one single-problem block with nbuf u buffers.
+constexpr int kLdsBytes = 160 * 1024;
+template <int MODE, int EX, int EZ>
+constexpr int block_lds_bytes(int nbuf) {
+  return nbuf * (EZ + 4) * (EX + 4) * 4 + (MODE == BMODE_ADJ ? EZ * EX * 4 : 0) + 8 * EZ + 64;
+}
+// u buffers: two when two blocks fit in one CU's LDS that way; else one if
+// that lets two blocks share a CU (one block's loads and stores then overlap
+// the other's steps, at the price of a second barrier per step); else two.
+// The recompute keeps two: with one it needs more registers than two blocks
+// leave.
+template <int MODE, int EX, int EZ>
+constexpr int block_nbuf() {
+  return 2 * block_lds_bytes<MODE, EX, EZ>(2) <= kLdsBytes                          ? 2
+         : MODE != BMODE_REC && 2 * block_lds_bytes<MODE, EX, EZ>(1) <= kLdsBytes ? 1
+                                                                                   : 2;
+}
+// Waves per SIMD that let two blocks share a CU (1: no constraint).
+template <int MODE, int EX, int EZ, int RZ>
+constexpr int block_waves_per_eu() {
+  return 2 * block_lds_bytes<MODE, EX, EZ>(block_nbuf<MODE, EX, EZ>()) <= kLdsBytes
+             ? (2 * (EX * (EZ / RZ) / 64) + 3) / 4
+             : 1;
+}
+
 template <int MODE, int EX, int EZ, int RZ, int TMAX>
-__global__ __launch_bounds__(EX *(EZ / RZ)) void fd_block(BlockArgs a) {
+__global__ __launch_bounds__(EX *(EZ / RZ))
+__attribute__((amdgpu_waves_per_eu(block_waves_per_eu<MODE, EX, EZ, RZ>()))) void fd_block(BlockArgs a) {
   constexpr int NTHREADS = EX * (EZ / RZ);
   constexpr int H = 2 * TMAX;                 // halo width
   constexpr int IX = EX - 2 * H, IZ = EZ - 2 * H;
   constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
   constexpr bool ADJ = MODE == BMODE_ADJ;
+  constexpr int NBUF = block_nbuf<MODE, EX, EZ>();
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
-  __shared__ float lds[2][EZ + 4][LW];
+  __shared__ float lds[NBUF][EZ + 4][LW];
   __shared__ float gzs[EZ];     // z damping of each extended-tile row (0 outside the grid)
   __shared__ int rrs[EZ];       // receiver-row index of each extended-tile row (-1: none)
   __shared__ float injs[TMAX];  // forward / recompute: source term w(t_n)/(dx dz) of each step
@@ -132,6 +162,7 @@ __device__ __forceinline__ void fd_block_multi_body(const BlockArgs &a, const in
   constexpr int IX = EX - 2 * H, IZ = EZ - 2 * H;
   constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
   constexpr bool ADJ = MODE == BMODE_ADJ;
+  constexpr int NBUF = 2;
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
   auto &lds = sh.u;
   auto &gzs = sh.gz;

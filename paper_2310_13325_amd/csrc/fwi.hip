@@ -630,8 +630,11 @@ static vip_status backward_sweep_blocked(const Emitter &emit, const FwiDims &D, 
       a.rho_stride = (long long)D.nt * D.nr;
       a.seg = P.seg;
       a.seg_stride = seg_stride;
+      a.acc32 = P.acc32;
       a.acc64 = acc64;
       a.acc64_stride = N;
+      a.acc_first = n == n1 - 1;
+      a.acc_flush = n - T + 1 == n0;
       VIP_TRY(emit(BMODE_ADJ, a));
       ++launches;
       adj_zero = false;
