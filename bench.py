@@ -44,12 +44,14 @@ ALU_PUBLISHED_TFLOPS = 157.3
 # form: read u, q, c and write u, q (20 B); the recompute also stores
 # a^n = L u^n + f^n (4 B), the adjoint reads it back (4 B).  Over the three
 # sweeps this is 68 B per point-step and shot.
-BYTES_PER_POINT_STEP = {"forward": 20.0, "recompute": 24.0, "adjoint": 24.0}
+BYTES_PER_POINT_STEP = {"forward": 20.0, "recompute": 24.0, "adjoint": 24.0,
+                        "forward_store": 24.0}
 # Algorithmic flops per point-step: the fourth-order Laplacian with symmetric
 # weights (4 pair sums, 1 centre product, 4 fused multiply-adds = 13), the
 # increment update q' = g (q + c L u), u' = g u + q' (5); the adjoint adds the
 # imaging product-sum z a (2).
-FLOPS_PER_POINT_STEP = {"forward": 18.0, "recompute": 18.0, "adjoint": 20.0}
+FLOPS_PER_POINT_STEP = {"forward": 18.0, "recompute": 18.0, "adjoint": 20.0,
+                        "forward_store": 18.0}
 COUNTERS = os.path.join(ROOT, "profiles", "fd_block_c2_counters.json")
 STEP_SOURCES = [os.path.join(ROOT, "paper_2310_13325_amd", "csrc", f)
                 for f in ("fwi.hip", "fd_block.h", "fd_block_body.inc")]
@@ -142,6 +144,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the gradient through a hipGraph")
+    ap.add_argument("--tile", type=int, default=None, help="fixed tile shape (no tile tuning)")
+    ap.add_argument("--stored-steps", type=int, default=None,
+                    help="fixed stored tail steps (no schedule tuning)")
+    ap.add_argument("--live-pairs", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="automatic tile, every segment recomputed, all pairs live")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -152,6 +160,7 @@ def main():
 
     import numpy as np
     import torch
+    from paper_2310_13325_amd import autotune
     from paper_2310_13325_amd import binding as vb
     from paper_2310_13325_amd import configs, synth
 
@@ -178,10 +187,35 @@ def main():
     G = grad.view(n, d)
     eps_holder = {}
 
-    def step(i):
+    # Untimed set-up: the autotuner picks the tile shape (all pairs live, every
+    # segment recomputed), then how to spend device memory on the gradient
+    # (stored tail steps, live pairs) within what is free.
+    sched = {"stored_steps": 0, "live_pairs": 0}
+
+    def grad_call(stored, live):
         vb.vip_grad_logpost(ctx, S["grid"], S["geom"], S["x"], S["dobs"], S["sigma"],
                             ckpt_every=prob.ckpt_every, lo=S["lo"], hi=S["hi"],
-                            logpost=logpost, grad=grad)
+                            logpost=logpost, grad=grad, stored_steps=stored, live_pairs=live)
+
+    key = autotune.key_for(S["grid"], n * prob.ns) + f":k{prob.ckpt_every}"
+    if args.tile is not None:
+        ctx.set_tile(args.tile)
+    elif not args.no_tune:
+        tile = autotune.tune(ctx, lambda: grad_call(0, 0), key, tiles=autotune.candidates(False))
+        log(f"autotuned tile {tile}")
+    if args.stored_steps is not None:
+        sched = {"stored_steps": args.stored_steps, "live_pairs": args.live_pairs}
+    elif not args.no_tune:
+        torch.cuda.empty_cache()
+        free = torch.cuda.mem_get_info()[0] + ctx.workspace_bytes()
+        budget = int(free - 8e9)
+        cands = autotune.schedules(S["grid"], S["geom"], n, prob.ckpt_every, budget)
+        best = autotune.tune_schedule(grad_call, key + ":sched", cands)
+        sched = {"stored_steps": best[0], "live_pairs": best[1]}
+        log(f"memory schedule {sched} from {cands}")
+
+    def step(i):
+        grad_call(sched["stored_steps"], sched["live_pairs"])
         if "eps" not in eps_holder:
             # step size giving updates of about 10 m/s (fixed after the first gradient)
             eps_holder["eps"] = 10.0 / float(G.abs().max())
@@ -236,9 +270,14 @@ def main():
                         "unit": "TFLOP/s",
                         "frac": round(kinds[dom]["alg_TFLOPs"] / ALU_PEAK_TFLOPS, 4),
                         "frac_of_published": round(kinds[dom]["alg_TFLOPs"] / ALU_PUBLISHED_TFLOPS, 4)},
-                "gradient_ceiling_pg_per_s": round(
-                    HBM_PEAK_GBS * 1e9 / (sum(BYTES_PER_POINT_STEP.values()) * prob.ns * prob.nt
-                                          * (prob.nx + 2 * prob.nb) * (prob.nz + 2 * prob.nb)), 1)}
+                # particle-gradients/s of a streaming implementation at the HBM
+                # peak: forward, recompute and adjoint sweeps (20 + 24 + 24 B per
+                # point-step and shot), or forward-with-store and adjoint (24 + 24)
+                "streaming_ceiling_pg_per_s": {
+                    label: round(HBM_PEAK_GBS * 1e9 / (b * prob.ns * (prob.nt - 1)
+                                                       * (prob.nx + 2 * prob.nb)
+                                                       * (prob.nz + 2 * prob.nb)), 1)
+                    for label, b in (("recompute", 68.0), ("stored", 48.0))}}
 
     extra = {}
     if not args.no_plain:
@@ -292,7 +331,8 @@ def main():
                                "+ 20-cell sponge, nt=2000, dt=2 ms, 10 shots, 200 receivers, "
                                "8 Hz Ricker, 128 particles, checkpoints every 50 steps",
                    "particles": n, "pairs_per_step": n * prob.ns, "graph": args.graph,
-                   "gram": "bf16", "parallelism": "1 GPU"},
+                   "gram": "bf16", "parallelism": "1 GPU", "tile": ctx.tile_for(S["grid"]),
+                   "stored_steps": sched["stored_steps"], "live_pairs": sched["live_pairs"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err": err,

@@ -144,12 +144,14 @@ int vip_version(void);
  * only), every contiguous run of step-kernel launches of one kind is
  * bracketed by HIP events on the stream it is enqueued on.  vip_read_timing
  * synchronises, sums the runs since the last read per kind (0 = forward,
- * 1 = recompute, 2 = adjoint) and forgets them: launches[k], ms[k] (event
- * time of the runs) and point_steps[k] (padded grid points x pairs advanced). */
+ * 1 = recompute, 2 = adjoint, 3 = forward that also stores a^n for the
+ * adjoint) and forgets them: launches[k], ms[k] (event time of the runs) and
+ * point_steps[k] (padded grid points x pairs advanced). */
+#define VIP_TIMING_KINDS 4
 typedef struct {
-  int64_t launches[3];
-  double ms[3];
-  double point_steps[3];
+  int64_t launches[VIP_TIMING_KINDS];
+  double ms[VIP_TIMING_KINDS];
+  double point_steps[VIP_TIMING_KINDS];
 } vip_timing;
 vip_status vip_set_timing(vip_ctx *ctx, int enable);
 vip_status vip_read_timing(vip_ctx *ctx, vip_timing *out);
@@ -179,11 +181,16 @@ vip_status vip_forward(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *g
 
 /* Workspace bytes for vip_grad_logpost.  ckpt_every = k: the forward state is
  * stored every k steps and each k-step segment is recomputed once during the
- * adjoint sweep (k >= nt-1 keeps one segment: the whole history).
- * live_pairs: how many (particle, shot) pairs are simulated at once
- * (0 = all np*ns); memory grows linearly with it. */
+ * adjoint sweep (k >= nt-1 keeps one segment).  stored_steps = S (0 .. nt-1):
+ * the last S steps form one segment whose a^n = L u^n + f^n the forward sweep
+ * keeps (S slots of a field per live pair), so the adjoint sweep recomputes
+ * only the first nt-1-S steps (with the one-step-per-launch kernel the tail
+ * is recomputed like any segment).  live_pairs: how many (particle, shot)
+ * pairs are simulated at once (0 = all np*ns); memory grows linearly with it.
+ * The memory/recompute trade-off changes only FP32 rounding order. */
 vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
-                                      int32_t ckpt_every, int32_t live_pairs, size_t *bytes);
+                                      int32_t ckpt_every, int32_t stored_steps,
+                                      int32_t live_pairs, size_t *bytes);
 
 /* For every particle p (vel[p], device float [np][nz][nx]):
  *   logpost[p] = -J_p + log prior,  J_p = 1/2 sum_{s,n,r} (d_{p,s,n,r} - dobs_{s,n,r})^2 / sigma^2
@@ -197,8 +204,9 @@ vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *
  * grad: device float [np][nz][nx].  prior may be NULL (no prior). */
 vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
                             const vip_prior *prior, int32_t np, const float *vel,
-                            const float *dobs, double sigma, int32_t ckpt_every, int32_t live_pairs,
-                            double *logpost, float *grad, void *ws, size_t ws_bytes);
+                            const float *dobs, double sigma, int32_t ckpt_every,
+                            int32_t stored_steps, int32_t live_pairs, double *logpost,
+                            float *grad, void *ws, size_t ws_bytes);
 
 /* Same result through the plain per-pair path: one pair at a time, one launch
  * per time step and per fused-away operation, global-memory stencil.  It exists

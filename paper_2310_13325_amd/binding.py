@@ -59,9 +59,12 @@ class VipSvgdLayout(ctypes.Structure):
                 ("L", ctypes.c_size_t), ("phi", ctypes.c_size_t)]
 
 
+TIMING_KINDS = ("forward", "recompute", "adjoint", "forward_store")
+
+
 class VipTiming(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 3), ("ms", ctypes.c_double * 3),
-                ("point_steps", ctypes.c_double * 3)]
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4),
+                ("point_steps", ctypes.c_double * 4)]
 
 
 class VipError(RuntimeError):
@@ -96,9 +99,9 @@ def lib() -> ctypes.CDLL:
             "vip_ricker": (ctypes.c_int, [vp, i32, dbl, dbl, dbl, vp]),
             "vip_forward_workspace": (ctypes.c_int, [G, GE, i32, szp]),
             "vip_forward": (ctypes.c_int, [vp, G, GE, i32, vp, vp, vp, sz]),
-            "vip_grad_logpost_workspace": (ctypes.c_int, [G, GE, i32, i32, i32, szp]),
-            "vip_grad_logpost": (ctypes.c_int, [vp, G, GE, PR, i32, vp, vp, dbl, i32, i32, vp, vp,
-                                                vp, sz]),
+            "vip_grad_logpost_workspace": (ctypes.c_int, [G, GE, i32, i32, i32, i32, szp]),
+            "vip_grad_logpost": (ctypes.c_int, [vp, G, GE, PR, i32, vp, vp, dbl, i32, i32, i32, vp,
+                                                vp, vp, sz]),
             "vip_grad_logpost_plain_workspace": (ctypes.c_int, [G, GE, i32, szp]),
             "vip_grad_logpost_plain": (ctypes.c_int, [vp, G, GE, PR, i32, vp, vp, dbl, vp, vp, vp,
                                                       sz]),
@@ -259,10 +262,15 @@ class Context:
         """Zero-initialised device workspace reused across calls with the same tag."""
         ws = self._ws.get(tag)
         if ws is None or ws.numel() < nbytes:
+            ws = None                       # release the smaller buffer before allocating
             self._ws.pop(tag, None)
             ws = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
             self._ws[tag] = ws
         return ws
+
+    def workspace_bytes(self) -> int:
+        """Device bytes held by this context's cached workspaces."""
+        return sum(int(w.numel()) for w in self._ws.values())
 
     def set_tile(self, tile: int):
         """-2 automatic, -1 one step per launch, 0.. a temporally blocked shape."""
@@ -283,7 +291,7 @@ class Context:
         """Per step-kernel kind (forward, recompute, adjoint): launches, ms, point-steps."""
         t = VipTiming()
         _check(lib().vip_read_timing(self._h, ctypes.byref(t)), "vip_read_timing")
-        kinds = ("forward", "recompute", "adjoint")
+        kinds = TIMING_KINDS
         return {k: {"launches": int(t.launches[i]), "ms": float(t.ms[i]),
                     "point_steps": float(t.point_steps[i])} for i, k in enumerate(kinds)}
 
@@ -325,23 +333,47 @@ def vip_forward(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
 
 
 def grad_logpost_workspace_bytes(grid: Grid, geom: Geometry, npart: int, ckpt_every: int,
-                                 live_pairs: int = 0) -> int:
+                                 live_pairs: int = 0, stored_steps: int = 0) -> int:
     g, ge = grid.c(), geom.c()
     nbytes = ctypes.c_size_t()
     _check(lib().vip_grad_logpost_workspace(ctypes.byref(g), ctypes.byref(ge), npart,
-                                            ckpt_every, live_pairs, ctypes.byref(nbytes)),
+                                            ckpt_every, stored_steps, live_pairs,
+                                            ctypes.byref(nbytes)),
            "vip_grad_logpost_workspace")
     return nbytes.value
+
+
+def stored_steps_for_budget(grid: Grid, geom: Geometry, npart: int, ckpt_every: int,
+                            budget_bytes: int, live_pairs: int = 0) -> int:
+    """Largest stored_steps S >= ckpt_every whose vip_grad_logpost workspace fits
+    budget_bytes, or 0.  For S >= k the workspace grows with S (one a^n slot per
+    stored step against two checkpoint fields per k steps), so bisection applies."""
+    k, m = min(ckpt_every, grid.nt - 1), grid.nt - 1
+    size = lambda s: grad_logpost_workspace_bytes(grid, geom, npart, ckpt_every, live_pairs, s)
+    if size(k) > budget_bytes:
+        return 0
+    lo, hi = k, m
+    if size(hi) <= budget_bytes:
+        return hi
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if size(mid) <= budget_bytes:
+            lo = mid
+        else:
+            hi = mid
+    return lo
 
 
 def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
                      dobs: torch.Tensor, sigma: float, ckpt_every: int = 50,
                      lo: Optional[torch.Tensor] = None, hi: Optional[torch.Tensor] = None,
                      live_pairs: int = 0, logpost: Optional[torch.Tensor] = None,
-                     grad: Optional[torch.Tensor] = None, ws_tag: str = "grad"):
+                     grad: Optional[torch.Tensor] = None, ws_tag: str = "grad",
+                     stored_steps: int = 0):
     ctx.sync_stream()
     npart = vel.shape[0]
-    nbytes = grad_logpost_workspace_bytes(grid, geom, npart, ckpt_every, live_pairs)
+    nbytes = grad_logpost_workspace_bytes(grid, geom, npart, ckpt_every, live_pairs,
+                                          stored_steps)
     ws = ctx.workspace(ws_tag, nbytes)
     if logpost is None:
         logpost = torch.empty(npart, dtype=torch.float64, device=ctx.device)
@@ -352,7 +384,8 @@ def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor
     _check(lib().vip_grad_logpost(ctx.handle, ctypes.byref(g), ctypes.byref(ge),
                                   ctypes.byref(pr) if pr is not None else None, npart,
                                   _ptr(vel, torch.float32), _ptr(dobs, torch.float32), sigma,
-                                  ckpt_every, live_pairs, _ptr(logpost, torch.float64),
+                                  ckpt_every, stored_steps, live_pairs,
+                                  _ptr(logpost, torch.float64),
                                   _ptr(grad, torch.float32), ctypes.c_void_p(ws.data_ptr()),
                                   ws.numel()), "vip_grad_logpost")
     return logpost, grad

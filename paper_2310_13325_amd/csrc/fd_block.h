@@ -34,7 +34,10 @@
 
 namespace vip {
 
-enum { BMODE_FWD = 0, BMODE_REC = 1, BMODE_ADJ = 2 };
+// Sweep modes: forward (traces), recompute (stores a^n), adjoint (reads a^n,
+// images), and forward that also stores a^n (the tail segment kept by the
+// forward sweep).
+enum { BMODE_FWD = 0, BMODE_REC = 1, BMODE_ADJ = 2, BMODE_FWS = 3 };
 
 // Raw buffer descriptor over one [N] float field (stride 0, N * 4 bytes, the
 // gfx9-family data-format word).  Offsets are bytes in the VGPR offset, which
@@ -58,7 +61,7 @@ struct BlockArgs {
   int pair0, ns, nt, nr;
   int steps;              // T <= TMAX
   int n_start;            // FWD/REC: first input time index; ADJ: first n (produces z^{n+1}), descending
-  int seg_n0;             // REC/ADJ: time index of segment slot 0
+  int seg_n0;             // REC/FWS/ADJ: time index of segment slot 0
   float w1x, w2x, w1z, w2z;   // Laplacian weights 4/3, -1/12 times 1/dx^2 (x) or 1/dz^2 (z)
   float inv_area;
   const float *gx, *gz, *c;
@@ -69,9 +72,9 @@ struct BlockArgs {
   long long in_stride;
   float *u_out, *q_out;   // null: the final state is not needed
   long long out_stride;
-  float *data;            // FWD: traces [pair][nt][nr]
+  float *data;            // FWD/FWS: traces [pair][nt][nr]
   long long data_stride;
-  float *seg;             // REC: a^n written at slot n - seg_n0; ADJ: read
+  float *seg;             // REC/FWS: a^n written at slot n - seg_n0; ADJ: read
   long long seg_stride;
   const float *rho;       // ADJ: residual [pair][nt][nr]
   long long rho_stride;
@@ -118,13 +121,14 @@ constexpr int block_lds_bytes(int nbuf) {
 // u buffers: two when two blocks fit in one CU's LDS that way; else one if
 // that lets two blocks share a CU (one block's loads and stores then overlap
 // the other's steps, at the price of a second barrier per step); else two.
-// The recompute keeps two: with one it needs more registers than two blocks
-// leave.
+// The modes that store a^n keep two: with one they need more registers than
+// two blocks leave.
 template <int MODE, int EX, int EZ>
 constexpr int block_nbuf() {
-  return 2 * block_lds_bytes<MODE, EX, EZ>(2) <= kLdsBytes                          ? 2
-         : MODE != BMODE_REC && 2 * block_lds_bytes<MODE, EX, EZ>(1) <= kLdsBytes ? 1
-                                                                                   : 2;
+  return 2 * block_lds_bytes<MODE, EX, EZ>(2) <= kLdsBytes ? 2
+         : MODE != BMODE_REC && MODE != BMODE_FWS && 2 * block_lds_bytes<MODE, EX, EZ>(1) <= kLdsBytes
+             ? 1
+             : 2;
 }
 // Waves per SIMD that let two blocks share a CU (1: no constraint).
 template <int MODE, int EX, int EZ, int RZ>

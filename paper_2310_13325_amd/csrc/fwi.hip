@@ -32,7 +32,8 @@
 
 namespace vip {
 
-enum { MODE_FWD = 0, MODE_REC = 1, MODE_ADJ = 2 };
+// step-kernel kinds (also the timing kinds; MODE_FWS: forward that stores a^n)
+enum { MODE_FWD = 0, MODE_REC = 1, MODE_ADJ = 2, MODE_FWS = 3 };
 
 struct StepArgs {
   int NX, NZ, N;
@@ -432,6 +433,7 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
   if (cfg == C) {                                                                      \
     if (mode == BMODE_FWD) fd_block<BMODE_FWD, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
     else if (mode == BMODE_REC) fd_block<BMODE_REC, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
+    else if (mode == BMODE_FWS) fd_block<BMODE_FWS, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
     else fd_block<BMODE_ADJ, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a);               \
     VIP_LAUNCH_CHECK();                                                                \
     return VIP_OK;                                                                     \
@@ -522,18 +524,26 @@ static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wav
   return a;
 }
 
+// Forward sweep for pairs [pair0, pair0 + npairs) (blocked kernel): traces
+// into data; with ckpt, the state at every segment start but the first into
+// ckpt [pair][nseg-1][2][N]; when the dimensions keep a tail segment and the
+// segment buffer exists, the tail's steps also store a^n into it.
 static vip_status forward_sweep_blocked(const Emitter &emit, const FwiDims &D, const FwiPlan &P,
                                         const float *wavelet, int pair0, int npairs, float *data,
                                         float *ckpt) {
   const long long N = D.N;
   const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
+  const long long seg_stride = (long long)D.seg_slots * N;
   const int tmax = kTiles[D.tile].tmax;
   const float *u_in = P.u[0], *q_in = P.q[0];
   long long in_stride = N;
-  int buf = 0, launches = 0;
-  const int run = emit.timing_begin_(MODE_FWD);
+  int buf = 0;
   for (int s = 0; s < D.nseg; ++s) {
-    const int n0 = s * D.k, n1 = std::min(n0 + D.k, D.nt - 1);
+    const int n0 = D.seg_begin(s), n1 = D.seg_end(s);
+    const bool store = P.seg && D.stored > 0 && s == D.nseg - 1;
+    const int mode = store ? BMODE_FWS : BMODE_FWD;
+    const int run = emit.timing_begin_(store ? MODE_FWS : MODE_FWD);
+    int launches = 0;
     for (int n = n0; n < n1; n += tmax) {
       const int T = std::min(tmax, n1 - n);
       BlockArgs a = block_args(D, P, wavelet, pair0);
@@ -556,14 +566,19 @@ static vip_status forward_sweep_blocked(const Emitter &emit, const FwiDims &D, c
       }
       a.data = data;
       a.data_stride = (long long)D.nt * D.nr;
-      VIP_TRY(emit(BMODE_FWD, a));
+      if (store) {
+        a.seg = P.seg;
+        a.seg_stride = seg_stride;
+        a.seg_n0 = n0;
+      }
+      VIP_TRY(emit(mode, a));
       ++launches;
       u_in = a.u_out;
       q_in = a.q_out;
       in_stride = a.out_stride;
     }
+    emit.timing_end_(run, launches, double(n1 - n0) * double(N) * npairs);
   }
-  emit.timing_end_(run, launches, double(D.nt - 1) * double(N) * npairs);
   return VIP_OK;
 }
 
@@ -572,19 +587,21 @@ static vip_status backward_sweep_blocked(const Emitter &emit, const FwiDims &D, 
                                          const float *rho, const float *ckpt, double *acc64) {
   const long long N = D.N;
   const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
-  const long long seg_stride = (long long)D.k * N;
+  const long long seg_stride = (long long)D.seg_slots * N;
   const int tmax = kTiles[D.tile].tmax;
   bool adj_zero = true;
   int abuf = 0;
   for (int s = D.nseg - 1; s >= 0; --s) {
-    const int n0 = s * D.k, n1 = std::min(n0 + D.k, D.nt - 1);
+    const int n0 = D.seg_begin(s), n1 = D.seg_end(s);
     const float *u_in = s == 0 ? P.u[0] : ckpt + (long long)(s - 1) * 2 * N;
     const float *q_in = s == 0 ? P.q[0] : u_in + N;
     long long in_stride = s == 0 ? N : ck_stride;
     bool zero = s == 0;
     int buf = 0, launches = 0;
-    const int run_rec = emit.timing_begin_(MODE_REC);
-    for (int n = n0; n < n1; n += tmax) {
+    // the forward sweep already stored the tail segment's a^n
+    const bool stored = D.stored > 0 && s == D.nseg - 1;
+    const int run_rec = stored ? -1 : emit.timing_begin_(MODE_REC);
+    for (int n = n0; n < n1 && !stored; n += tmax) {
       const int T = std::min(tmax, n1 - n);
       BlockArgs a = block_args(D, P, wavelet, pair0);
       a.steps = T;
@@ -645,8 +662,9 @@ static vip_status backward_sweep_blocked(const Emitter &emit, const FwiDims &D, 
 }
 
 // Forward sweep for pairs [pair0, pair0 + npairs): traces into data (indexed by
-// local pair, stride nt*nr); optional checkpoints (u, q) at steps s*k, s >= 1,
-// into ckpt [pair][nseg-1][2][N].
+// local pair, stride nt*nr); optional checkpoints (u, q) at every segment
+// start but the first into ckpt [pair][nseg-1][2][N].  (This kernel leaves
+// the tail segment's a^n to the backward sweep.)
 static vip_status forward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
                                        const float *wavelet, int pair0, int npairs, float *data,
                                        float *ckpt) {
@@ -655,6 +673,7 @@ static vip_status forward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const Fwi
   const float *u_in = nullptr, *q_in = nullptr;
   long long in_stride = N;
   const int run = timing_begin(ctx, MODE_FWD);
+  int next_seg = 1;   // next segment whose start state is checkpointed
   for (int n = 0; n <= D.nt - 2; ++n) {
     StepArgs a = base_args(D, P, wavelet, pair0);
     a.n = n;
@@ -663,8 +682,9 @@ static vip_status forward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const Fwi
     a.q_in = n == 0 ? P.q[0] : q_in;
     a.in_stride = in_stride;
     const int m = n + 1;
-    if (ckpt && m % D.k == 0 && m / D.k <= D.nseg - 1) {
-      a.u_out = ckpt + (long long)(m / D.k - 1) * 2 * N;
+    if (ckpt && next_seg < D.nseg && m == D.seg_begin(next_seg)) {
+      a.u_out = ckpt + (long long)(next_seg - 1) * 2 * N;
+      ++next_seg;
       a.q_out = a.u_out + N;
       a.out_stride = ck_stride;
     } else {
@@ -691,12 +711,12 @@ static vip_status backward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const Fw
                                         const float *rho, const float *ckpt, double *acc64) {
   const long long N = D.N;
   const long long ck_stride = (long long)(D.nseg - 1) * 2 * N;
-  const long long seg_stride = (long long)D.k * N;
+  const long long seg_stride = (long long)D.seg_slots * N;
   int adj_steps = 0;
   const float *z_in = nullptr, *Q_in = nullptr;
   for (int s = D.nseg - 1; s >= 0; --s) {
-    const int n0 = s * D.k;
-    const int n1 = std::min(n0 + D.k, D.nt - 1);
+    const int n0 = D.seg_begin(s);
+    const int n1 = D.seg_end(s);
     const float *u_in = nullptr, *q_in = nullptr;
     long long in_stride = N;
     const int run_rec = timing_begin(ctx, MODE_REC);
@@ -908,10 +928,11 @@ vip_status vip_forward(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *g
 }
 
 vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *geom, int32_t np,
-                                      int32_t ckpt_every, int32_t live_pairs, size_t *bytes) {
+                                      int32_t ckpt_every, int32_t stored_steps,
+                                      int32_t live_pairs, size_t *bytes) {
   if (!bytes) return VIP_E_ARG;
   FwiDims D;
-  VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, false, &D));
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, false, &D, stored_steps));
   FwiPlan P;
   plan_fwi(D, nullptr, PLAN_GRAD, &P);
   *bytes = P.bytes;
@@ -920,15 +941,16 @@ vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *
 
 vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
                             const vip_prior *prior, int32_t np, const float *vel,
-                            const float *dobs, double sigma, int32_t ckpt_every, int32_t live_pairs,
-                            double *logpost, float *grad, void *ws, size_t ws_bytes) {
+                            const float *dobs, double sigma, int32_t ckpt_every,
+                            int32_t stored_steps, int32_t live_pairs, double *logpost,
+                            float *grad, void *ws, size_t ws_bytes) {
   if (!ctx || !vel || !dobs || !logpost || !grad || !ws) return VIP_E_ARG;
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return VIP_E_ARG;
   if (prior && prior->kind != VIP_PRIOR_NONE &&
       (prior->kind != VIP_PRIOR_UNIFORM_CLIP || !prior->lo || !prior->hi))
     return VIP_E_ARG;
   FwiDims D;
-  VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, true, &D));
+  VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, true, &D, stored_steps));
   apply_tile_choice(ctx, &D);
   FwiPlan P;
   plan_fwi(D, static_cast<char *>(ws), PLAN_GRAD, &P);
@@ -936,6 +958,7 @@ vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
   VIP_TRY_HIP(hipSetDevice(ctx->device));
   KeyBuilder kb;
   kb.add(std::string("grad")).add(D.tile).add(*grid).add(np).add(vel).add(dobs).add(sigma).add(ckpt_every)
+      .add(stored_steps)
       .add(live_pairs).add(logpost).add(grad).add(ws).add(geom->wavelet).add(geom->ns)
       .add(geom->nr);
   kb.add(prior ? prior->kind : -1).add(prior ? prior->lo : nullptr).add(prior ? prior->hi : nullptr);

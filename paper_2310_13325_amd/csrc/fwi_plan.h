@@ -15,7 +15,18 @@ struct FwiDims {
   long long N;          // padded points per field
   int ns, nr, np;
   long long pairs;      // np * ns, pair = particle * ns + shot
-  int k, nseg;          // checkpoint interval, segments over a-indices 0 .. nt-2
+  // Steps n = 0 .. nt-2 (u^n -> u^{n+1}) fall into segments: regular ones of
+  // k steps over [0, n_split) and, when stored > 0, one tail segment
+  // [n_split, nt-1) of the last `stored` steps.  The state at every segment
+  // start but the first is checkpointed; the backward sweep recomputes each
+  // segment's a^n from it, except the tail's when the forward stores them.
+  int k, nseg;          // checkpoint interval, number of segments
+  int stored;           // steps in the tail segment (0: none)
+  int n_split;          // first step of the tail segment (nt-1 when stored == 0)
+  int nseg_r;           // regular segments
+  int seg_slots;        // a^n slots of the segment buffer (the longest segment)
+  int seg_begin(int s) const { return s < nseg_r ? s * k : n_split; }
+  int seg_end(int s) const { return s + 1 < nseg ? seg_begin(s + 1) : nt - 1; }
   long long live;       // pairs simulated at once
   int nrows;            // distinct receiver rows
   int rz;               // rows per thread in the streaming step kernel (tile height 4*rz)
@@ -40,7 +51,8 @@ int tile_count();
 inline int default_rz(int NZ) { return NZ >= 96 ? 8 : (NZ >= 40 ? 4 : 2); }
 
 inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int32_t np,
-                            int32_t ckpt_every, int32_t live, bool need_wavelet, FwiDims *D) {
+                            int32_t ckpt_every, int32_t live, bool need_wavelet, FwiDims *D,
+                            int32_t stored_steps = 0) {
   if (!grid || !geom || !D) return VIP_E_ARG;
   const vip_grid &g = *grid;
   if (g.nx < 1 || g.nz < 1 || g.nb < 0 || g.nt < 2) return VIP_E_ARG;
@@ -67,6 +79,7 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
   }
   if (courant_factor(g) > 1.0) return VIP_E_CFL;
   if (ckpt_every < 1 || live < 0) return VIP_E_ARG;
+  if (stored_steps < 0 || stored_steps > g.nt - 1) return VIP_E_ARG;
   FwiDims d;
   d.nx = g.nx;
   d.nz = g.nz;
@@ -82,7 +95,11 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
   d.pairs = (long long)np * geom->ns;
   if (d.pairs >= (1LL << 31)) return VIP_E_UNSUPPORTED;
   d.k = std::min(ckpt_every, g.nt - 1);
-  d.nseg = (g.nt - 1 + d.k - 1) / d.k;
+  d.stored = stored_steps;
+  d.n_split = g.nt - 1 - stored_steps;
+  d.nseg_r = (d.n_split + d.k - 1) / d.k;
+  d.nseg = d.nseg_r + (stored_steps > 0 ? 1 : 0);
+  d.seg_slots = std::max(d.nseg_r > 0 ? std::min(d.k, d.n_split) : 0, stored_steps);
   d.live = live == 0 ? d.pairs : std::min<long long>(live, d.pairs);
   {
     std::vector<int> rows(geom->rec_iz, geom->rec_iz + geom->nr);
@@ -142,12 +159,12 @@ inline void plan_fwi(const FwiDims &D, char *base, int kind, FwiPlan *P) {
   }
   if (kind == PLAN_GRAD) {
     P->ckpt = A.take<float>(size_t(live) * size_t(D.nseg - 1) * 2 * D.N);
-    P->seg = A.take<float>(size_t(live) * size_t(D.k) * D.N);
+    P->seg = A.take<float>(size_t(live) * size_t(D.seg_slots) * D.N);
     P->acc32 = A.take<float>(field);
     P->resid = A.take<float>(size_t(live) * D.nt * D.nr);
     P->J = A.take<double>(D.pairs);
   } else if (kind == PLAN_TAPE) {
-    P->seg = A.take<float>(size_t(live) * size_t(D.k) * D.N);
+    P->seg = A.take<float>(size_t(live) * size_t(D.seg_slots) * D.N);
     P->acc32 = A.take<float>(field);
   } else if (kind == PLAN_PLAIN) {
     P->hist = A.take<float>(size_t(D.nt - 1) * D.N);

@@ -211,7 +211,7 @@ vip_status vip_read_timing(vip_ctx *ctx, vip_timing *out) {
   for (auto &r : ctx->runs) {
     float ms = 0.0f;
     VIP_TRY_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
-    if (r.kind >= 0 && r.kind < 3) {
+    if (r.kind >= 0 && r.kind < VIP_TIMING_KINDS) {
       out->launches[r.kind] += r.launches;
       out->ms[r.kind] += double(ms);
       out->point_steps[r.kind] += r.point_steps;

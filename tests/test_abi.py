@@ -48,12 +48,12 @@ def _geom(nx=64, rec_iz=2, rec_ix=None):
     return vb.Geometry([1, 1], [10, 40], [rec_iz] * len(rec_ix), rec_ix, None)
 
 
-def _ws(grid, geom, npart=4, k=50, live=0):
+def _ws(grid, geom, npart=4, k=50, live=0, stored=0):
     lib = vb.lib()
     nbytes = ctypes.c_size_t(0)
     g, ge = grid.c(), geom.c()
-    st = lib.vip_grad_logpost_workspace(ctypes.byref(g), ctypes.byref(ge), npart, k, live,
-                                        ctypes.byref(nbytes))
+    st = lib.vip_grad_logpost_workspace(ctypes.byref(g), ctypes.byref(ge), npart, k, stored,
+                                        live, ctypes.byref(nbytes))
     return st, nbytes.value
 
 
@@ -68,6 +68,19 @@ def test_workspace_queries_and_validation():
     assert _ws(_grid(), _geom(rec_iz=48))[0] == -1           # receiver row outside
     assert _ws(_grid(), _geom(rec_ix=[3, 3]))[0] == -1       # two receivers, one node
     assert _ws(_grid(nt=1), _geom())[0] == -1
+    # stored tail segment: valid 0 .. nt-1, one a^n field per stored step and
+    # live pair beyond the k-step segment buffer, one checkpoint (2 fields) less
+    # per k steps it covers
+    g, ge = _grid(), _geom()
+    nt, N = g.nt, (g.nx + 2 * g.nb) * (g.nz + 2 * g.nb)
+    assert _ws(g, ge, stored=-1)[0] == -1 and _ws(g, ge, stored=nt)[0] == -1
+    pairs = 4 * 2
+    st0, b0 = _ws(g, ge, k=50)
+    st1, b1 = _ws(g, ge, k=50, stored=100)
+    assert st0 == 0 and st1 == 0
+    nseg0 = -(-(nt - 1) // 50)
+    nseg1 = -(-(nt - 1 - 100) // 50) + 1
+    assert b1 - b0 == pairs * N * 4 * ((100 - 50) - 2 * (nseg0 - nseg1))
     assert _ws(_grid(), _geom(), k=0)[0] == -1
     assert _ws(_grid(), _geom(), npart=0)[0] == -1
     nb = ctypes.c_size_t(0)

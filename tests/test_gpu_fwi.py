@@ -125,6 +125,44 @@ def test_grad_ragged_segments_and_chunks(tile):
     c.set_tile(-2)
 
 
+@pytest.mark.parametrize("tile", [-1, 0, 2])
+def test_grad_stored_tail_segment(tile):
+    """The forward sweep keeps a^n of the last S steps (the blocked kernel stores
+    them as it goes, the one-step kernel recomputes them from a checkpoint):
+    same gradient as S = 0 up to the regrouping of FP32 segment sums, and the
+    oracle's; S covers a multiple of the interval, a ragged value and all steps."""
+    prob = small_problem(nt=181)
+    case = build_case(prob)
+    c = ctx()
+    c.set_tile(tile)
+    grid, geom = grid_geom(c, case)
+    args = (c, grid, geom, dev(case.particles), dev(case.dobs), case.sigma)
+    kw = dict(ckpt_every=13, lo=dev(case.lo), hi=dev(case.hi))
+    lp0, g0 = vb.vip_grad_logpost(*args, **kw, ws_tag="s0")
+    g0 = g0.cpu().numpy()
+    lp_ref, g_ref = _oracle_grad(case, case.particles)
+    for S in (26, 57, 180):
+        c.read_timing()
+        c.set_timing(True)
+        lp_s, g_s = vb.vip_grad_logpost(*args, **kw, stored_steps=S, ws_tag=f"s{S}")
+        c.set_timing(False)
+        tm = c.read_timing()
+        g_s = g_s.cpu().numpy()
+        e0, eo = rel(g_s, g0), max(rel(g_s[p], g_ref[p]) for p in range(g_s.shape[0]))
+        print(f"tile {tile} stored {S}: vs S=0 {e0:.2e}, vs oracle {eo:.2e}, "
+              f"recompute point-steps {tm['recompute']['point_steps']:.3g}", flush=True)
+        assert e0 <= 1e-6 and eo <= GRAD_TOL
+        assert np.allclose(lp_s.cpu().numpy(), lp0.cpu().numpy(), rtol=1e-6, atol=0)
+        pts = float(grid.nx + 2 * grid.nb) * (grid.nz + 2 * grid.nb) * case.particles.shape[0] * prob.ns
+        if tile >= 0:   # the blocked forward stores the tail: only the rest is recomputed
+            assert tm["recompute"]["point_steps"] == pts * (prob.nt - 1 - S)
+            assert tm["forward_store"]["point_steps"] == pts * S
+        else:
+            assert tm["recompute"]["point_steps"] == pts * (prob.nt - 1)
+    assert c.poll(c.workspace("s180", 0)) == 0
+    c.set_tile(-2)
+
+
 def test_rerun_is_bitwise_identical():
     case = build_case(configs.C1)
     c = ctx()
