@@ -18,8 +18,8 @@
 //               unsigned integers), then h^2 = med / (2 ln(n+1)) (1 if med = 0)
 //   rbf         K = exp(-D / (2 h^2)), row sums s (FP64 sums)
 //   cholesky    (sSVGD) L = chol(K / n) in FP64 in LDS, jitter retries
-//   update      one FP32 register-tiled GEMM pass computing K G, K Xc (and L Xi),
-//               then phi, the update and the clip in its epilogue.
+//   update      one FP32 register-tiled GEMM pass computing K (G - Xc / h^2) (and
+//               L Xi), then phi, the update and the clip in its epilogue.
 // Distances come from centred particles: D is translation invariant, and
 // centring removes the large common velocity that BF16 could not resolve.
 #include <cmath>
@@ -41,19 +41,40 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 }
 
 // ---- centre ----------------------------------------------------------------
-__global__ void centre_kernel(const float *x, float *xbar, float *xc, uint16_t *xc16, int n,
-                              long long d, uint32_t *status) {
-  long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= d) return;
-  double s = 0.0;
-  for (int i = 0; i < n; ++i) s += double(x[(long long)i * d + a]);
-  float m = float(s / double(n));
-  if (!isfinite(m)) atomicOr(status, VIP_FLAG_NONFINITE);
-  xbar[a] = m;
-  for (int i = 0; i < n; ++i) {
-    float v = x[(long long)i * d + a] - m;
-    xc[(long long)i * d + a] = v;
-    xc16[(long long)i * d + a] = f32_to_bf16_rne(v);
+// Block of 64 coordinates x 16 row groups: each thread sums every 16th
+// particle of its coordinate (FP64), the 16 partial sums are added in a fixed
+// order, and the block then writes the centred columns.
+constexpr int CENTRE_COLS = 64, CENTRE_GROUPS = 16;
+__global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
+    const float *x, float *xbar, float *xc, uint16_t *xc16, int n, long long d, uint32_t *status) {
+  __shared__ double part[CENTRE_GROUPS][CENTRE_COLS];
+  __shared__ float mean[CENTRE_COLS];
+  const int tx = threadIdx.x % CENTRE_COLS, ty = threadIdx.x / CENTRE_COLS;
+  const long long a = (long long)blockIdx.x * CENTRE_COLS + tx;
+  const bool in = a < d;
+  double sum = 0.0;
+  if (in)
+    for (int i = ty; i < n; i += CENTRE_GROUPS) sum += double(x[(long long)i * d + a]);
+  part[ty][tx] = sum;
+  __syncthreads();
+  if (ty == 0) {
+    double t = 0.0;
+    for (int g = 0; g < CENTRE_GROUPS; ++g) t += part[g][tx];
+    const float m = float(t / double(n));
+    mean[tx] = m;
+    if (in) {
+      xbar[a] = m;
+      if (!isfinite(m)) atomicOr(status, VIP_FLAG_NONFINITE);
+    }
+  }
+  __syncthreads();
+  if (!in) return;
+  const float m = mean[tx];
+  for (int i = ty; i < n; i += CENTRE_GROUPS) {
+    const long long e = (long long)i * d + a;
+    const float v = x[e] - m;
+    xc[e] = v;
+    xc16[e] = f32_to_bf16_rne(v);
   }
 }
 
@@ -366,6 +387,10 @@ __global__ void philox_fill_kernel(float *out, long long count, uint32_t k0, uin
 // j staged 16 at a time.  Accumulates KG = K G, KX = K Xc and, with NOISE,
 // LX = L Xi; the epilogue forms phi, writes it, and updates x in place (x is
 // read only at the element this thread writes).
+// phi_i = 1/n [ sum_j K_ij (g_j - xc_j / h^2) + s_i xc_i / h^2 ]: the two
+// products K G and K Xc of eq:phi_mean regrouped into one, B = G - Xc / h^2
+// formed while staging tiles (its FP32 rounding bound, eps s_i (|g| + |xc| / h^2),
+// is the one the two separate products have).
 template <bool NOISE>
 __global__ __launch_bounds__(256) void update_kernel(const float *K, const float *Lf,
                                                      const float *g, const float *xc,
@@ -377,15 +402,15 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ float Ak[BK][BM + 4];
   __shared__ float Al[NOISE ? BK : 1][BM + 4];
-  __shared__ float Bg[BK][BN + 4];
-  __shared__ float Bx[BK][BN + 4];
+  __shared__ float Bb[BK][BN + 4];
   __shared__ float Bz[NOISE ? BK : 1][BN + 4];
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   const long long a0 = (long long)blockIdx.x * BN;
   const int i0 = blockIdx.y * BM;
-  float kg[4][4], kx[4][4], lz[4][4];
+  const float inv_h2 = float(1.0 / h2[0]);
+  float kb[4][4], lz[4][4];
   for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) kg[r][c] = kx[r][c] = lz[r][c] = 0.0f;
+    for (int c = 0; c < 4; ++c) kb[r][c] = lz[r][c] = 0.0f;
   for (int j0 = 0; j0 < n; j0 += BK) {
     for (int it = 0; it < 4; ++it) {
       int idx = t + it * 256;             // 64 rows x 16 j
@@ -396,18 +421,16 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
       int jr = idx >> 6, ac = idx & 63;   // 16 j x 64 coordinates
       bool okb = (j0 + jr < n) && (a0 + ac < d);
       long long src = (long long)(j0 + jr) * d + a0 + ac;
-      Bg[jr][ac] = okb ? g[src] : 0.0f;
-      Bx[jr][ac] = okb ? xc[src] : 0.0f;
+      Bb[jr][ac] = okb ? fmaf(-xc[src], inv_h2, g[src]) : 0.0f;
       if (NOISE) Bz[jr][ac] = okb ? xi[src] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < BK; ++jj) {
-      float av[4], bg[4], bx[4], al[4], bz[4];
+      float av[4], bb[4], al[4], bz[4];
       for (int e = 0; e < 4; ++e) {
         av[e] = Ak[jj][ty * 4 + e];
-        bg[e] = Bg[jj][tx * 4 + e];
-        bx[e] = Bx[jj][tx * 4 + e];
+        bb[e] = Bb[jj][tx * 4 + e];
         if (NOISE) {
           al[e] = Al[jj][ty * 4 + e];
           bz[e] = Bz[jj][tx * 4 + e];
@@ -415,25 +438,23 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
       }
       for (int r = 0; r < 4; ++r)
         for (int c = 0; c < 4; ++c) {
-          kg[r][c] = fmaf(av[r], bg[c], kg[r][c]);
-          kx[r][c] = fmaf(av[r], bx[c], kx[r][c]);
+          kb[r][c] = fmaf(av[r], bb[c], kb[r][c]);
           if (NOISE) lz[r][c] = fmaf(al[r], bz[c], lz[r][c]);
         }
     }
     __syncthreads();
   }
-  const float inv_h2 = float(1.0 / h2[0]);
   const float inv_n = 1.0f / float(n);
   bool bad = false;
   for (int r = 0; r < 4; ++r) {
     int i = i0 + ty * 4 + r;
     if (i >= n) break;
-    const float si = s[i];
+    const float si = s[i] * inv_h2;
     for (int c = 0; c < 4; ++c) {
       long long a = a0 + tx * 4 + c;
       if (a >= d) break;
       long long e = (long long)i * d + a;
-      float p = (kg[r][c] + (si * xc[e] - kx[r][c]) * inv_h2) * inv_n;
+      float p = fmaf(si, xc[e], kb[r][c]) * inv_n;
       phi[e] = p;
       float v = x[e] + eps * p;
       if (NOISE) v += noise_scale * lz[r][c];
@@ -474,8 +495,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   const long long nn = (long long)n * n;
   const unsigned nn_blocks = unsigned((nn + 255) / 256);
 
-  centre_kernel<<<dim3(unsigned((d + 255) / 256)), dim3(256), 0, s>>>(x, P.xbar, P.xc, P.xc16, n,
-                                                                      d, P.status);
+  centre_kernel<<<dim3(unsigned((d + CENTRE_COLS - 1) / CENTRE_COLS)),
+                  dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(x, P.xbar, P.xc, P.xc16, n, d,
+                                                             P.status);
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;
   dim3 ggrid(unsigned(nup * P.splits));
