@@ -18,8 +18,9 @@
 //               unsigned integers), then h^2 = med / (2 ln(n+1)) (1 if med = 0)
 //   rbf         K = exp(-D / (2 h^2)), row sums s (FP64 sums)
 //   cholesky    (sSVGD) L = chol(K / n) in FP64 in LDS, jitter retries
-//   update      one FP32 register-tiled GEMM pass computing K (G - Xc / h^2) (and
-//               L Xi), then phi, the update and the clip in its epilogue.
+//   update      one GEMM pass computing K (G - Xc / h^2) (on the FP32 matrix
+//               cores; with noise, and L Xi, on the vector units), then phi,
+//               the update and the clip in its epilogue.
 // Distances come from centred particles: D is translation invariant, and
 // centring removes the large common velocity that BF16 could not resolve.
 #include <cmath>
@@ -466,6 +467,128 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
+// The same update (without noise) with the product on the FP32 matrix cores
+// (v_mfma_f32_32x32x2_f32: lane l holds A[l % 32][l / 32] and B[l / 32][l % 32];
+// result register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]).
+// Block: 128 particles x 128 coordinates, 4 waves of 2 x 2 tiles of 32 x 32;
+// the particle index j of the product runs in stages of 16 through LDS, the
+// next stage's tiles prefetched into registers during the current one.  K is
+// symmetric (bitwise: G is mirrored and D_ij, D_ji add the same two diagonal
+// terms), so the A tile K[i][j0 + k] is read as rows j0 + k of K.  Blocks that
+// share a column range are consecutive per XCD, so its B tiles meet in one L2.
+constexpr int UM = 128, UN = 128, UK = 16, UP = 4;
+__global__ __launch_bounds__(256) void update_mfma_kernel(const float *K, const float *g,
+                                                          const float *xc, const float *s,
+                                                          const double *h2, float *x, float *phi,
+                                                          const float *lo, const float *hi, int n,
+                                                          long long d, int mblocks, int vec,
+                                                          float eps, uint32_t *status) {
+  __shared__ __attribute__((aligned(16))) float As[UK][UM + UP];   // As[k][i] = K[i][j0 + k]
+  __shared__ __attribute__((aligned(16))) float Bs[UK][UN + UP];   // Bs[k][a] = B[j0 + k][a0 + a]
+  // tile index, contiguous per XCD (blocks are dealt round-robin over 8 XCDs)
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  const int nt = mblocks * int((d + UN - 1) / UN);
+  if (tb >= nt) return;
+  const int i0 = (tb % mblocks) * UM;
+  const long long a0 = (long long)(tb / mblocks) * UN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const float inv_h2 = float(1.0 / h2[0]);
+
+  // staging: thread t loads 4 float4 of A (rows k = t / 32 + 8 e, columns 4 (t % 32))
+  // and 2 float4 of g and xc each (rows k = t / 32 + 8 e, columns 4 (t % 32))
+  const int sk = t >> 5, sc = (t & 31) * 4;
+  float4 pa[2], pg[2], px[2];
+  auto load_stage = [&](int j0) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = sk + 8 * e, j = j0 + k;
+      pa[e] = pg[e] = px[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j < n) {
+        const int ii = i0 + sc;
+        if (vec && ii + 3 < n) {
+          pa[e] = *reinterpret_cast<const float4 *>(K + (long long)j * n + ii);
+        } else {
+          float tmp[4];
+          for (int q = 0; q < 4; ++q) tmp[q] = (ii + q < n) ? K[(long long)j * n + ii + q] : 0.f;
+          pa[e] = make_float4(tmp[0], tmp[1], tmp[2], tmp[3]);
+        }
+        const long long aa = a0 + sc;
+        const long long src = (long long)j * d + aa;
+        if (vec && aa + 3 < d) {
+          pg[e] = *reinterpret_cast<const float4 *>(g + src);
+          px[e] = *reinterpret_cast<const float4 *>(xc + src);
+        } else {
+          float tg[4], tx[4];
+          for (int q = 0; q < 4; ++q) {
+            tg[q] = (aa + q < d) ? g[src + q] : 0.f;
+            tx[q] = (aa + q < d) ? xc[src + q] : 0.f;
+          }
+          pg[e] = make_float4(tg[0], tg[1], tg[2], tg[3]);
+          px[e] = make_float4(tx[0], tx[1], tx[2], tx[3]);
+        }
+      }
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = sk + 8 * e;
+      *reinterpret_cast<float4 *>(&As[k][sc]) = pa[e];
+      float4 bv;
+      bv.x = fmaf(-px[e].x, inv_h2, pg[e].x);
+      bv.y = fmaf(-px[e].y, inv_h2, pg[e].y);
+      bv.z = fmaf(-px[e].z, inv_h2, pg[e].z);
+      bv.w = fmaf(-px[e].w, inv_h2, pg[e].w);
+      *reinterpret_cast<float4 *>(&Bs[k][sc]) = bv;
+    }
+  };
+
+  f32x16_t acc[2][2];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 2; ++q)
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  load_stage(0);
+  for (int j0 = 0; j0 < n; j0 += UK) {
+    __syncthreads();               // the previous stage's tiles are no longer read
+    store_stage();
+    __syncthreads();
+    if (j0 + UK < n) load_stage(j0 + UK);
+#pragma unroll
+    for (int kk = 0; kk < UK; kk += 2) {
+      const int k = kk + (lane >> 5);
+      float fa[2], fb[2];
+      for (int m = 0; m < 2; ++m) fa[m] = As[k][wi * 64 + m * 32 + (lane & 31)];
+      for (int q = 0; q < 2; ++q) fb[q] = Bs[k][wj * 64 + q * 32 + (lane & 31)];
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m], fb[q], acc[m][q], 0, 0, 0);
+    }
+  }
+
+  const float inv_n = 1.0f / float(n);
+  bool bad = false;
+  for (int m = 0; m < 2; ++m)
+    for (int r = 0; r < 16; ++r) {
+      const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (i >= n) continue;
+      const float si = s[i] * inv_h2;
+      for (int q = 0; q < 2; ++q) {
+        const long long a = a0 + wj * 64 + q * 32 + (lane & 31);
+        if (a >= d) continue;
+        const long long e = (long long)i * d + a;
+        const float p = fmaf(si, xc[e], acc[m][q][r]) * inv_n;
+        phi[e] = p;
+        float v = x[e] + eps * p;
+        if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
+        bad |= !isfinite(v);
+        x[e] = v;
+      }
+    }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+}
+
 // ---- host ---------------------------------------------------------------------
 
 static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
@@ -552,9 +675,15 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                                                     lo, hi, n, d, float(eps),
                                                     float(std::sqrt(2.0 * eps)), P.status);
   } else {
-    update_kernel<false><<<ugrid, dim3(256), 0, s>>>(P.K, nullptr, g, P.xc, nullptr, P.s, P.h2, x,
-                                                     P.phi, lo, hi, n, d, float(eps), 0.0f,
-                                                     P.status);
+    const int mblocks = (n + UM - 1) / UM;
+    const long long ntiles = (long long)mblocks * ((d + UN - 1) / UN);
+    if (ntiles >= (1LL << 30)) return VIP_E_UNSUPPORTED;
+    // float4 staging needs rows of a multiple of 4 floats and 16-byte aligned bases
+    const int vec = (d % 4 == 0) && (n % 4 == 0) && (reinterpret_cast<uintptr_t>(g) % 16 == 0) &&
+                    (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
+                    (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
+    update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(256), 0, s>>>(
+        P.K, g, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), P.status);
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;
