@@ -470,19 +470,20 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
 // The same update (without noise) with the product on the FP32 matrix cores
 // (v_mfma_f32_32x32x2_f32: lane l holds A[l % 32][l / 32] and B[l / 32][l % 32];
 // result register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]).
-// Block: 128 particles x 128 coordinates, 4 waves of 2 x 2 tiles of 32 x 32;
-// the particle index j of the product runs in stages of 16 through LDS, the
-// next stage's tiles prefetched into registers during the current one.  K is
-// symmetric (bitwise: G is mirrored and D_ij, D_ji add the same two diagonal
-// terms), so the A tile K[i][j0 + k] is read as rows j0 + k of K.  Blocks that
-// share a column range are consecutive per XCD, so its B tiles meet in one L2.
-constexpr int UM = 128, UN = 128, UK = 16, UP = 4;
-__global__ __launch_bounds__(256) void update_mfma_kernel(const float *K, const float *g,
-                                                          const float *xc, const float *s,
-                                                          const double *h2, float *x, float *phi,
-                                                          const float *lo, const float *hi, int n,
-                                                          long long d, int mblocks, int vec,
-                                                          float eps, uint32_t *status) {
+// Block: 256 particles x 128 coordinates, 8 waves (4 x 2) of 2 x 2 tiles of
+// 32 x 32; the particle index j of the product runs in stages of 16 through
+// LDS, the next stage's tiles prefetched into registers during the current
+// one.  K is symmetric (bitwise: G is mirrored and D_ij, D_ji add the same two
+// diagonal terms), so the A tile K[i][j0 + k] is read as rows j0 + k of K.
+// Blocks that share a column range are consecutive per XCD, so its B tiles
+// meet in one L2.
+constexpr int UM = 256, UN = 128, UK = 16, UP = 4, UT = 512;
+__global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const float *g,
+                                                         const float *xc, const float *s,
+                                                         const double *h2, float *x, float *phi,
+                                                         const float *lo, const float *hi, int n,
+                                                         long long d, int mblocks, int vec,
+                                                         float eps, uint32_t *status) {
   __shared__ __attribute__((aligned(16))) float As[UK][UM + UP];   // As[k][i] = K[i][j0 + k]
   __shared__ __attribute__((aligned(16))) float Bs[UK][UN + UP];   // Bs[k][a] = B[j0 + k][a0 + a]
   // tile index, contiguous per XCD (blocks are dealt round-robin over 8 XCDs)
@@ -496,53 +497,39 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(const float *K, const 
   const int wi = w >> 1, wj = w & 1;
   const float inv_h2 = float(1.0 / h2[0]);
 
-  // staging: thread t loads 4 float4 of A (rows k = t / 32 + 8 e, columns 4 (t % 32))
-  // and 2 float4 of g and xc each (rows k = t / 32 + 8 e, columns 4 (t % 32))
-  const int sk = t >> 5, sc = (t & 31) * 4;
-  float4 pa[2], pg[2], px[2];
+  // staging: A rows k = t / 64 + 8 e (e = 0, 1), columns 4 (t % 64); B row
+  // k = t / 32, columns 4 (t % 32)
+  const int ak = t >> 6, ac = (t & 63) * 4;
+  const int bk = t >> 5, bc = (t & 31) * 4;
+  float4 pa[2], pg, px;
+  auto load4 = [&](const float *base, long long off, long long lim) {
+    if (vec && off + 3 < lim) return *reinterpret_cast<const float4 *>(base + off);
+    float tmp[4];
+    for (int q = 0; q < 4; ++q) tmp[q] = (off + q < lim) ? base[off + q] : 0.f;
+    return make_float4(tmp[0], tmp[1], tmp[2], tmp[3]);
+  };
   auto load_stage = [&](int j0) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int k = sk + 8 * e, j = j0 + k;
-      pa[e] = pg[e] = px[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (j < n) {
-        const int ii = i0 + sc;
-        if (vec && ii + 3 < n) {
-          pa[e] = *reinterpret_cast<const float4 *>(K + (long long)j * n + ii);
-        } else {
-          float tmp[4];
-          for (int q = 0; q < 4; ++q) tmp[q] = (ii + q < n) ? K[(long long)j * n + ii + q] : 0.f;
-          pa[e] = make_float4(tmp[0], tmp[1], tmp[2], tmp[3]);
-        }
-        const long long aa = a0 + sc;
-        const long long src = (long long)j * d + aa;
-        if (vec && aa + 3 < d) {
-          pg[e] = *reinterpret_cast<const float4 *>(g + src);
-          px[e] = *reinterpret_cast<const float4 *>(xc + src);
-        } else {
-          float tg[4], tx[4];
-          for (int q = 0; q < 4; ++q) {
-            tg[q] = (aa + q < d) ? g[src + q] : 0.f;
-            tx[q] = (aa + q < d) ? xc[src + q] : 0.f;
-          }
-          pg[e] = make_float4(tg[0], tg[1], tg[2], tg[3]);
-          px[e] = make_float4(tx[0], tx[1], tx[2], tx[3]);
-        }
-      }
+      const int j = j0 + ak + 8 * e;
+      pa[e] = j < n ? load4(K + (long long)j * n, i0 + ac, n) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int j = j0 + bk;
+    pg = px = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j < n) {
+      pg = load4(g + (long long)j * d, a0 + bc, d);
+      px = load4(xc + (long long)j * d, a0 + bc, d);
     }
   };
   auto store_stage = [&]() {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int k = sk + 8 * e;
-      *reinterpret_cast<float4 *>(&As[k][sc]) = pa[e];
-      float4 bv;
-      bv.x = fmaf(-px[e].x, inv_h2, pg[e].x);
-      bv.y = fmaf(-px[e].y, inv_h2, pg[e].y);
-      bv.z = fmaf(-px[e].z, inv_h2, pg[e].z);
-      bv.w = fmaf(-px[e].w, inv_h2, pg[e].w);
-      *reinterpret_cast<float4 *>(&Bs[k][sc]) = bv;
-    }
+    for (int e = 0; e < 2; ++e) *reinterpret_cast<float4 *>(&As[ak + 8 * e][ac]) = pa[e];
+    float4 bv;
+    bv.x = fmaf(-px.x, inv_h2, pg.x);
+    bv.y = fmaf(-px.y, inv_h2, pg.y);
+    bv.z = fmaf(-px.z, inv_h2, pg.z);
+    bv.w = fmaf(-px.w, inv_h2, pg.w);
+    *reinterpret_cast<float4 *>(&Bs[bk][bc]) = bv;
   };
 
   f32x16_t acc[2][2];
@@ -682,7 +669,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     const int vec = (d % 4 == 0) && (n % 4 == 0) && (reinterpret_cast<uintptr_t>(g) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
-    update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(256), 0, s>>>(
+    update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
         P.K, g, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), P.status);
   }
   VIP_LAUNCH_CHECK();
