@@ -11,7 +11,7 @@
 //   centre      xbar = mean_i x_i (FP64 sums); Xc = X - xbar in FP32 and BF16
 //   gram        partial Gram blocks of Xc Xc^T over split ranges of d:
 //               BF16 on matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation)
-//               or FP32 on the vector units
+//               or FP32 on matrix cores (v_mfma_f32_32x32x2_f32)
 //   reduce      G = sum of the partials (fixed order), D_ij = G_ii + G_jj - 2 G_ij
 //   median      exact k-th order statistics of the D values by 4-pass radix
 //               select on their IEEE bits (non-negative floats order like
@@ -166,13 +166,17 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, fl
       }
 }
 
-// ---- Gram, FP32 vector units -------------------------------------------------
-// Same 128x128 blocks; each thread owns an 8x8 sub-block, k staged 16 at a time.
+// ---- Gram, FP32 matrix cores -------------------------------------------------
+// Same 128x128 blocks and k splits; 4 waves, each a 64x64 sub-block as 2x2
+// tiles of v_mfma_f32_32x32x2_f32 (lane l holds A[l % 32][l / 32] and
+// B[l / 32][l % 32]; result register r of lane l is C[8 (r / 4) + 4 (l / 32) +
+// r % 4][l % 32]).  k is staged 16 at a time, stored k-major in LDS so that
+// each half-wave reads 32 consecutive rows.
+constexpr int GF_K = 16, GF_P = 4;
 __global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, float *part, int n,
                                                        long long d, long long kspan, int nbt) {
-  constexpr int BK = 16;
-  __shared__ float As[BK][GB + 4];
-  __shared__ float Bs[BK][GB + 4];
+  __shared__ __attribute__((aligned(16))) float As[GF_K][GB + GF_P];
+  __shared__ __attribute__((aligned(16))) float Bs[GF_K][GB + GF_P];
   const int nup = nbt * (nbt + 1) / 2;
   const int split = blockIdx.x / nup;
   int bi, bj;
@@ -180,37 +184,59 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, float *p
   const int i0 = bi * GB, j0 = bj * GB;
   const long long k0 = (long long)split * kspan;
   const long long k1 = min(d, k0 + kspan);
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  float acc[8][8];
-  for (int a = 0; a < 8; ++a)
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0f;
-  for (long long kb = k0; kb < k1; kb += BK) {
-    for (int it = 0; it < 8; ++it) {
-      int idx = t + it * 256;        // 0 .. 2047 = 128 rows x 16 k
-      int row = idx >> 4, kk = idx & 15;
-      long long k = kb + kk;
-      As[kk][row] = (i0 + row < n && k < k1) ? xc[(long long)(i0 + row) * d + k] : 0.0f;
-      Bs[kk][row] = (j0 + row < n && k < k1) ? xc[(long long)(j0 + row) * d + k] : 0.0f;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const bool vec = (d % 4) == 0 && (kspan % 4) == 0;
+  f32x16_t acc[2][2];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 2; ++q)
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  for (long long kb = k0; kb < k1; kb += GF_K) {
+    // 128 rows x 16 k per operand: 4 threads per row, a float4 each, two rows per thread
+    for (int it = 0; it < 2; ++it) {
+      const int idx = t + it * 256;
+      const int row = idx >> 2, kq = (idx & 3) * 4;
+      const long long k = kb + kq;
+      float va[4], vb[4];
+      if (vec && k + 3 < k1) {
+        const float4 fa = i0 + row < n ? *reinterpret_cast<const float4 *>(xc + (long long)(i0 + row) * d + k)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 fb = j0 + row < n ? *reinterpret_cast<const float4 *>(xc + (long long)(j0 + row) * d + k)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+        va[0] = fa.x; va[1] = fa.y; va[2] = fa.z; va[3] = fa.w;
+        vb[0] = fb.x; vb[1] = fb.y; vb[2] = fb.z; vb[3] = fb.w;
+      } else {
+        for (int c = 0; c < 4; ++c) {
+          va[c] = (i0 + row < n && k + c < k1) ? xc[(long long)(i0 + row) * d + k + c] : 0.0f;
+          vb[c] = (j0 + row < n && k + c < k1) ? xc[(long long)(j0 + row) * d + k + c] : 0.0f;
+        }
+      }
+      for (int c = 0; c < 4; ++c) {
+        As[kq + c][row] = va[c];
+        Bs[kq + c][row] = vb[c];
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      float av[8], bv[8];
-      for (int e = 0; e < 8; ++e) {
-        av[e] = As[kk][ty * 8 + e];
-        bv[e] = Bs[kk][tx * 8 + e];
-      }
-      for (int a = 0; a < 8; ++a)
-        for (int b = 0; b < 8; ++b) acc[a][b] = fmaf(av[a], bv[b], acc[a][b]);
+    for (int kk = 0; kk < GF_K; kk += 2) {
+      const int k = kk + (lane >> 5);
+      float fa[2], fb[2];
+      for (int m = 0; m < 2; ++m) fa[m] = As[k][wi * 64 + m * 32 + (lane & 31)];
+      for (int q = 0; q < 2; ++q) fb[q] = Bs[k][wj * 64 + q * 32 + (lane & 31)];
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m], fb[q], acc[m][q], 0, 0, 0);
     }
     __syncthreads();
   }
   float *P = part + (long long)split * n * n;
-  for (int a = 0; a < 8; ++a)
-    for (int b = 0; b < 8; ++b) {
-      int row = i0 + ty * 8 + a, col = j0 + tx * 8 + b;
-      if (row < n && col < n) P[(long long)row * n + col] = acc[a][b];
-    }
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 2; ++q)
+      for (int r = 0; r < 16; ++r) {
+        int row = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        int col = j0 + wj * 64 + q * 32 + (lane & 31);
+        if (row < n && col < n) P[(long long)row * n + col] = acc[m][q][r];
+      }
 }
 
 // G = sum_s part[s] in split order; entries of lower blocks mirror the upper ones.

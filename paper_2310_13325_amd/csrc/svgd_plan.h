@@ -28,6 +28,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   const int nup = P->nbt * (P->nbt + 1) / 2;
   int splits = std::max(1, std::min(64, (512 + nup - 1) / nup));
   long long span = (d + splits - 1) / splits;
+  span = (span + 15) / 16 * 16;   // k ranges start on 16-element boundaries (vector loads)
   span = std::max<long long>(256, (span + 63) / 64 * 64);
   P->kspan = span;
   P->splits = int((d + span - 1) / span);
