@@ -70,15 +70,16 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters():
+def traffic_from_counters(configuration: dict):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source in the same configuration (tile
+    shape, stored steps, live pairs)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("source_sha256_16") != source_hash():
+    if c.get("source_sha256_16") != source_hash() or c.get("configuration") != configuration:
         return None
     return c.get("traffic_bytes_per_launch")
 
@@ -187,9 +188,9 @@ def main():
     G = grad.view(n, d)
     eps_holder = {}
 
-    # Untimed set-up: the autotuner picks the tile shape (all pairs live, every
-    # segment recomputed), then how to spend device memory on the gradient
-    # (stored tail steps, live pairs) within what is free.
+    # Untimed set-up: the autotuner times every tile shape under every memory
+    # schedule (stored tail steps, live pairs) that fits the free HBM and keeps
+    # the fastest pair; --tile / --stored-steps fix either, --no-tune both.
     sched = {"stored_steps": 0, "live_pairs": 0}
 
     def grad_call(stored, live):
@@ -197,22 +198,21 @@ def main():
                             ckpt_every=prob.ckpt_every, lo=S["lo"], hi=S["hi"],
                             logpost=logpost, grad=grad, stored_steps=stored, live_pairs=live)
 
-    key = autotune.key_for(S["grid"], n * prob.ns) + f":k{prob.ckpt_every}"
     if args.tile is not None:
         ctx.set_tile(args.tile)
-    elif not args.no_tune:
-        tile = autotune.tune(ctx, lambda: grad_call(0, 0), key, tiles=autotune.candidates(False))
-        log(f"autotuned tile {tile}")
     if args.stored_steps is not None:
         sched = {"stored_steps": args.stored_steps, "live_pairs": args.live_pairs}
-    elif not args.no_tune:
+    if not args.no_tune and (args.tile is None or args.stored_steps is None):
         torch.cuda.empty_cache()
         free = torch.cuda.mem_get_info()[0] + ctx.workspace_bytes()
         budget = int(free - 8e9)
-        cands = autotune.schedules(S["grid"], S["geom"], n, prob.ckpt_every, budget)
-        best = autotune.tune_schedule(grad_call, key + ":sched", cands)
-        sched = {"stored_steps": best[0], "live_pairs": best[1]}
-        log(f"memory schedule {sched} from {cands}")
+        cands = ([(sched["stored_steps"], sched["live_pairs"])] if args.stored_steps is not None
+                 else autotune.schedules(S["grid"], S["geom"], n, prob.ckpt_every, budget))
+        tiles = [args.tile] if args.tile is not None else None
+        tile, st, live, tm = autotune.tune_joint(ctx, grad_call, cands, tiles=tiles)
+        sched = {"stored_steps": st, "live_pairs": live}
+        log(f"autotuned tile {tile}, memory schedule {sched} over {len(tm)} candidates "
+            f"(schedules {cands})")
 
     def step(i):
         grad_call(sched["stored_steps"], sched["live_pairs"])
@@ -261,7 +261,8 @@ def main():
                         "share_of_step": round(t["ms"] / 1e3 / elapsed, 3)}
     dom = max(kinds, key=lambda k: kinds[k]["share_of_step"])
     ach = kinds[dom]["alg_GBps"]
-    traffic = traffic_from_counters()
+    traffic = traffic_from_counters({"tile": tile, "stored_steps": sched["stored_steps"],
+                                     "live_pairs": sched["live_pairs"]})
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else traffic.get(dom),

@@ -143,3 +143,23 @@ def tune_schedule(fn: Callable[[int, int], object], key: str, cands,
         table.put(key, -2, {f"{s}/{live}": t for (s, live), t in timings.items()},
                   stored_steps=best[0], live_pairs=best[1])
     return best
+
+
+def tune_joint(ctx: vb.Context, fn: Callable[[int, int], object], cands,
+               tiles: Optional[Iterable[int]] = None, reps: int = 1):
+    """Time fn(stored_steps, live_pairs) for every tile shape and schedule in
+    `cands` (the best tile depends on the schedule: keeping every step trades
+    the recompute sweep for a store in the forward one) and keep the fastest.
+    Leaves the context set to the chosen tile; returns (tile, stored, live, timings)."""
+    timings = {}
+    for t in (candidates(False) if tiles is None else tiles):
+        ctx.set_tile(t)
+        for st, live in cands:
+            try:
+                timings[(t, st, live)] = time_ms(lambda: fn(st, live), reps)
+            except vb.VipError as e:
+                if e.status != -7:
+                    raise
+    best = min(timings, key=timings.get)
+    ctx.set_tile(best[0])
+    return best[0], best[1], best[2], timings
