@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-minibatch", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the gradient through a hipGraph")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile shape (no tile tuning)")
     ap.add_argument("--stored-steps", type=int, default=None,
@@ -281,6 +282,29 @@ def main():
                     for label, b in (("recompute", 68.0), ("stored", 48.0))}}
 
     extra = {}
+    if not args.no_minibatch:
+        # Section 2.4's minibatch gradients: b of the 10 shots per iteration,
+        # drawn uniformly without replacement, each an unbiased estimate
+        ctx._ws.pop("grad", None)
+        torch.cuda.empty_cache()
+        b = 2
+        subsets = synth.minibatch_shots(prob.seed, prob.ns, b, 6)
+        mb = lambda shots: vb.vip_grad_logpost_minibatch(
+            ctx, S["grid"], S["geom"], S["x"], S["dobs"], S["sigma"], shots,
+            ckpt_every=prob.ckpt_every, lo=S["lo"], hi=S["hi"], logpost=logpost, grad=grad,
+            stored_steps=sched["stored_steps"], ws_tag="minibatch")
+        mb(subsets[0])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for shots in subsets[1:]:
+            mb(shots)
+        torch.cuda.synchronize()
+        rate = (len(subsets) - 1) * n / (time.perf_counter() - t)
+        extra["minibatch"] = {"shots_per_batch": b, "of_shots": prob.ns, "value": round(rate, 2),
+                              "unit": "particle-gradient estimates/s",
+                              "vs_full": round(rate / value, 2)}
+        ctx._ws.pop("minibatch", None)
+        log(f"minibatch {b} of {prob.ns} shots: {rate:.1f} estimates/s")
     if not args.no_plain:
         x1 = S["x"][:1].contiguous()
         vb.vip_grad_logpost_plain(ctx, S["grid"], S["geom"], x1, S["dobs"], S["sigma"],

@@ -84,13 +84,20 @@ typedef struct {
  * same nr receivers.  Indices are interior cell indices (0 <= ix < nx,
  * 0 <= iz < nz), host arrays.  wavelet is the source time function w(t_n),
  * device float [nt]; the source term is w(t_n)/(dx dz) at the shot node
- * (vip_ricker fills a Ricker wavelet). */
+ * (vip_ricker fills a Ricker wavelet).
+ * shot_index (host [ns], or NULL for 0 .. ns-1) names the row of the observed
+ * data holding each listed shot, and nobs the number of rows (0 .. nobs-1;
+ * ignored when shot_index is NULL).  A geometry listing a random subset of a
+ * survey's shots, read in place from the full d_obs, gives the minibatch
+ * gradients of section 2.4 (with sigma scaled as in vip_grad_logpost). */
 typedef struct {
   int32_t ns;
   const int32_t *src_ix, *src_iz;
   int32_t nr;
   const int32_t *rec_ix, *rec_iz;
   const float *wavelet;
+  const int32_t *shot_index;
+  int32_t nobs;
 } vip_geometry;
 
 /* Prior (section 3): VIP_PRIOR_NONE, or a uniform prior on [lo, hi] per
@@ -200,8 +207,12 @@ vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *
  * forward sweep with checkpoints, then per segment a recompute sweep and an
  * adjoint sweep with the imaging sum accumulated in FP64 across segments and
  * shots.
- * dobs: device float [ns][nt][nr].  logpost: device double [np].
- * grad: device float [np][nz][nx].  prior may be NULL (no prior). */
+ * dobs: device float [ns][nt][nr] (or [nobs][nt][nr] read through the
+ * geometry's shot_index).  logpost: device double [np].
+ * grad: device float [np][nz][nx].  prior may be NULL (no prior).
+ * Minibatch (section 2.4, uniformly random data subsets): for b of a survey's
+ * S shots, sigma * sqrt(b / S) makes J the unbiased estimate (S / b) sum over
+ * the subset of the per-shot misfits, and its gradient likewise. */
 vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
                             const vip_prior *prior, int32_t np, const float *vel,
                             const float *dobs, double sigma, int32_t ckpt_every,

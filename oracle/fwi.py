@@ -298,3 +298,31 @@ def grad_logpost(vels, grid: Grid, geom: Geometry, dobs, sigma, lo=None, hi=None
         logpost[p] = -J + lp
         grad[p] = -dJ + glp
     return logpost, grad
+
+
+def minibatch_grad_logpost(vels, grid: Grid, geom: Geometry, dobs, sigma, shots, lo=None,
+                           hi=None):
+    """Section 2.4: the gradient of log p computed from uniformly random data
+    subsets -- here a subset of the shots -- is a stochastic approximation; the
+    log-likelihood of the subset scaled by ns / |subset| has the full-data value
+    as its expectation over subsets, and so has its gradient.  dobs holds every
+    shot of the survey; `shots` lists the subset (any order)."""
+    vels = np.asarray(vels, dtype=np.float64)
+    shots = [int(s) for s in shots]
+    scale = geom.ns / len(shots)
+    g = sponge(grid)
+    w = ricker(grid.nt, grid.dt, geom.f0, geom.t0)
+    logpost = np.zeros(vels.shape[0])
+    grad = np.zeros_like(vels)
+    for p in range(vels.shape[0]):
+        v_pad, c = coefficient(vels[p], grid)
+        J = 0.0
+        gpad = np.zeros((grid.NZ, grid.NX))
+        for s in shots:
+            Js, gs = shot_gradient(c, g, v_pad, grid, geom, s, dobs[s], sigma, w)
+            J += Js
+            gpad += gs
+        lp, glp = (0.0, 0.0) if lo is None else uniform_log_prior(vels[p], lo, hi)
+        logpost[p] = -scale * J + lp
+        grad[p] = -scale * fold_edge(gpad, grid.nb) + glp
+    return logpost, grad

@@ -12,6 +12,7 @@ vip_svgd_step, vip_ssvgd_step (plus the tape, plain-path and batching calls).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -47,7 +48,7 @@ class VipGrid(ctypes.Structure):
 class VipGeometry(ctypes.Structure):
     _fields_ = [("ns", ctypes.c_int32), ("src_ix", _i32p), ("src_iz", _i32p),
                 ("nr", ctypes.c_int32), ("rec_ix", _i32p), ("rec_iz", _i32p),
-                ("wavelet", ctypes.c_void_p)]
+                ("wavelet", ctypes.c_void_p), ("shot_index", _i32p), ("nobs", ctypes.c_int32)]
 
 
 class VipPrior(ctypes.Structure):
@@ -179,13 +180,26 @@ class Geometry:
     """Shot / receiver interior indices (host) and the device wavelet."""
 
     def __init__(self, src_iz: Sequence[int], src_ix: Sequence[int], rec_iz: Sequence[int],
-                 rec_ix: Sequence[int], wavelet: torch.Tensor):
+                 rec_ix: Sequence[int], wavelet: torch.Tensor,
+                 shot_index: Optional[Sequence[int]] = None, nobs: int = 0):
         self.src_iz = np.ascontiguousarray(src_iz, dtype=np.int32)
         self.src_ix = np.ascontiguousarray(src_ix, dtype=np.int32)
         self.rec_iz = np.ascontiguousarray(rec_iz, dtype=np.int32)
         self.rec_ix = np.ascontiguousarray(rec_ix, dtype=np.int32)
         assert len(self.src_iz) == len(self.src_ix) and len(self.rec_iz) == len(self.rec_ix)
         self.wavelet = wavelet
+        self.shot_index = (None if shot_index is None
+                           else np.ascontiguousarray(shot_index, dtype=np.int32))
+        self.nobs = int(nobs)
+
+    def subset(self, shots: Sequence[int]) -> "Geometry":
+        """The shots `shots` of this survey, reading their observed data in place
+        (rows `shots` of the full d_obs)."""
+        shots = np.asarray(shots, dtype=np.int64)
+        rows = shots if self.shot_index is None else self.shot_index[shots]
+        return Geometry(self.src_iz[shots], self.src_ix[shots], self.rec_iz, self.rec_ix,
+                        self.wavelet, shot_index=rows,
+                        nobs=self.nobs if self.shot_index is not None else self.ns)
 
     @property
     def ns(self):
@@ -198,8 +212,9 @@ class Geometry:
     def c(self) -> VipGeometry:
         p = lambda a: a.ctypes.data_as(_i32p)
         w = self.wavelet.data_ptr() if self.wavelet is not None else None
+        si = p(self.shot_index) if self.shot_index is not None else None
         return VipGeometry(self.ns, p(self.src_ix), p(self.src_iz), self.nr, p(self.rec_ix),
-                           p(self.rec_iz), w)
+                           p(self.rec_iz), w, si, self.nobs)
 
 
 def _prior(lo: Optional[torch.Tensor], hi: Optional[torch.Tensor]):
@@ -389,6 +404,16 @@ def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor
                                   _ptr(grad, torch.float32), ctypes.c_void_p(ws.data_ptr()),
                                   ws.numel()), "vip_grad_logpost")
     return logpost, grad
+
+
+def vip_grad_logpost_minibatch(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
+                               dobs: torch.Tensor, sigma: float, shots: Sequence[int], **kw):
+    """Unbiased minibatch estimate (section 2.4) from the shots `shots` of the
+    survey `geom` (observed data dobs [ns][nt][nr], read in place): the
+    log-likelihood and its gradient scaled by ns / len(shots), through sigma."""
+    sub = geom.subset(shots)
+    scale = len(shots) / (geom.nobs if geom.shot_index is not None else geom.ns)
+    return vip_grad_logpost(ctx, grid, sub, vel, dobs, sigma * math.sqrt(scale), **kw)
 
 
 def vip_grad_logpost_plain(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,

@@ -203,14 +203,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Residual rho = (d - dobs)/sigma^2 in place and J = 1/2 sum (d - dobs)^2/sigma^2
 // per pair (FP64, fixed reduction order).
 __global__ __launch_bounds__(256) void residual_kernel(float *d, long long d_stride,
-                                                       const float *dobs, int pair0, int ns,
-                                                       long long per_pair, double inv_s2,
-                                                       double *J, uint32_t *status) {
+                                                       const float *dobs, const int *shot_row,
+                                                       int pair0, int ns, long long per_pair,
+                                                       double inv_s2, double *J,
+                                                       uint32_t *status) {
   __shared__ double part[4];
   const int lp = blockIdx.x;
   const int shot = (pair0 + lp) % ns;
   float *dp = d + lp * d_stride;
-  const float *op = dobs + (long long)shot * per_pair;
+  const float *op = dobs + (long long)shot_row[shot] * per_pair;
   double acc = 0.0;
   for (long long e = threadIdx.x; e < per_pair; e += 256) {
     double r = double(dp[e]) - double(op[e]);
@@ -344,6 +345,9 @@ vip_status upload_tables(vip_ctx *ctx, const FwiDims &D, const vip_grid *grid,
     rmap[size_t(rrow[Z]) * D.NX + X] = r;   // nodes are distinct (checked in make_dims)
   }
   VIP_TRY(upload_i32(s, P.src, src.data(), src.size()));
+  std::vector<int32_t> shot_row(D.ns);
+  for (int k = 0; k < D.ns; ++k) shot_row[k] = geom->shot_index ? geom->shot_index[k] : k;
+  VIP_TRY(upload_i32(s, P.shot_row, shot_row.data(), shot_row.size()));
   VIP_TRY(upload_i32(s, P.rrow, rrow.data(), rrow.size()));
   VIP_TRY(upload_i32(s, P.rmap, rmap.data(), rmap.size()));
   return VIP_OK;
@@ -795,7 +799,8 @@ vip_status launch_residual(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, int
                            int npairs, const float *dobs, double sigma) {
   long long per_pair = (long long)D.nt * D.nr;
   residual_kernel<<<dim3(npairs), dim3(256), 0, ctx->s()>>>(
-      P.resid, per_pair, dobs, pair0, D.ns, per_pair, 1.0 / (sigma * sigma), P.J, P.status);
+      P.resid, per_pair, dobs, P.shot_row, pair0, D.ns, per_pair, 1.0 / (sigma * sigma), P.J,
+      P.status);
   VIP_LAUNCH_CHECK();
   return VIP_OK;
 }

@@ -70,6 +70,11 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
     if (geom->rec_ix[r] < 0 || geom->rec_ix[r] >= g.nx || geom->rec_iz[r] < 0 ||
         geom->rec_iz[r] >= g.nz)
       return VIP_E_ARG;
+  if (geom->shot_index) {
+    if (geom->nobs < 1) return VIP_E_ARG;
+    for (int s = 0; s < geom->ns; ++s)
+      if (geom->shot_index[s] < 0 || geom->shot_index[s] >= geom->nobs) return VIP_E_ARG;
+  }
   {
     // receivers must sit on distinct nodes (each node maps to one trace)
     std::vector<long long> nodes(geom->nr);
@@ -123,6 +128,7 @@ struct FwiPlan {
   uint32_t *status = nullptr;
   float *gx = nullptr, *gz = nullptr;
   int32_t *src = nullptr, *rrow = nullptr, *rmap = nullptr;
+  int32_t *shot_row = nullptr;   // row of d_obs holding each shot
   float *c = nullptr;
   float *u[2] = {nullptr, nullptr}, *q[2] = {nullptr, nullptr};
   float *z[2] = {nullptr, nullptr}, *Q[2] = {nullptr, nullptr};
@@ -141,6 +147,7 @@ inline void plan_fwi(const FwiDims &D, char *base, int kind, FwiPlan *P) {
   P->gx = A.take<float>(D.NX);
   P->gz = A.take<float>(D.NZ);
   P->src = A.take<int32_t>(D.ns);
+  P->shot_row = A.take<int32_t>(D.ns);
   P->rrow = A.take<int32_t>(D.NZ);
   P->rmap = A.take<int32_t>(size_t(D.nrows) * D.NX);
   P->c = A.take<float>(size_t(D.np) * D.N);

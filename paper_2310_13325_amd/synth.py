@@ -21,19 +21,21 @@ available; these recipes stand in for them:
   background, i.e. a 2 km/s interval per depth with a 1.5 km/s floor
   (section 4.2).
 * initial particles i.i.d. uniform within the prior (section 4.2).
-* every random stream derives from numpy SeedSequence(seed).spawn(6):
+* every random stream derives from numpy SeedSequence(seed).spawn(7):
   [model, data noise, particles, sSVGD normals, finite-difference cells,
-  SVGD-precision fields].
+  SVGD-precision fields, minibatch shot subsets] (the i-th child of a
+  SeedSequence does not depend on how many are spawned).
 """
 from __future__ import annotations
 
 import numpy as np
 
-STREAM_MODEL, STREAM_NOISE, STREAM_PARTICLES, STREAM_XI, STREAM_FDCELLS, STREAM_C5 = range(6)
+(STREAM_MODEL, STREAM_NOISE, STREAM_PARTICLES, STREAM_XI, STREAM_FDCELLS, STREAM_C5,
+ STREAM_MINIBATCH) = range(7)
 
 
 def rng(seed: int, stream: int) -> np.random.Generator:
-    return np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[stream])
+    return np.random.default_rng(np.random.SeedSequence(seed).spawn(7)[stream])
 
 
 def layers_anomalies(nz: int, nx: int, r: np.random.Generator) -> np.ndarray:
@@ -149,3 +151,10 @@ def svgd_precision_case(case, v_center):
     X = v_center[None] + case.spread * zeta
     G = -(X - v_center[None]) / case.spread ** 2 + 1e-4 * r.standard_normal(X.shape)
     return X.reshape(case.n, -1), G.reshape(case.n, -1)
+
+
+def minibatch_shots(seed: int, ns: int, b: int, iterations: int) -> np.ndarray:
+    """[iterations][b] shot subsets, each drawn uniformly without replacement
+    (section 2.4's uniformly random data subsets; passed to both sides)."""
+    r = rng(seed, STREAM_MINIBATCH)
+    return np.stack([r.choice(ns, size=b, replace=False) for _ in range(iterations)])

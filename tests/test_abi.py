@@ -68,6 +68,12 @@ def test_workspace_queries_and_validation():
     assert _ws(_grid(), _geom(rec_iz=48))[0] == -1           # receiver row outside
     assert _ws(_grid(), _geom(rec_ix=[3, 3]))[0] == -1       # two receivers, one node
     assert _ws(_grid(nt=1), _geom())[0] == -1
+    # minibatch geometry: rows of d_obs must exist
+    full = _geom()
+    assert _ws(_grid(), full.subset([1]))[0] == 0
+    bad = vb.Geometry(full.src_iz[:1], full.src_ix[:1], full.rec_iz, full.rec_ix, None,
+                      shot_index=[2], nobs=2)
+    assert _ws(_grid(), bad)[0] == -1
     # stored tail segment: valid 0 .. nt-1, one a^n field per stored step and
     # live pair beyond the k-step segment buffer, one checkpoint (2 fields) less
     # per k steps it covers

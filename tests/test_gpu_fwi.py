@@ -163,6 +163,34 @@ def test_grad_stored_tail_segment(tile):
     c.set_tile(-2)
 
 
+@pytest.mark.parametrize("tile", [-1, 0, 2])
+def test_minibatch_shot_subsets_match_oracle(tile):
+    """Section 2.4 minibatches: a subset of the shots, read in place from the
+    full d_obs, scaled by ns / b (through sigma); every shot in another order
+    gives the full-data value."""
+    prob = small_problem(nt=181, ns=4)
+    case = build_case(prob)
+    c = ctx()
+    c.set_tile(tile)
+    grid, geom = grid_geom(c, case)
+    x, dobs = dev(case.particles), dev(case.dobs)
+    kw = dict(ckpt_every=13, lo=dev(case.lo), hi=dev(case.hi))
+    for shots in ([3, 1], [2], [1, 3, 0, 2]):
+        lp, g = vb.vip_grad_logpost_minibatch(c, grid, geom, x, dobs, case.sigma, shots, **kw,
+                                              ws_tag="mb")
+        lp_ref, g_ref = ofwi.minibatch_grad_logpost(case.particles, case.ogrid, case.ogeom,
+                                                    case.dobs, case.sigma, shots, case.lo, case.hi)
+        g = g.cpu().numpy()
+        e = max(rel(g[p], g_ref[p]) for p in range(g.shape[0]))
+        print(f"tile {tile} minibatch {shots}: grad rel L2 {e:.2e}", flush=True)
+        assert e <= GRAD_TOL
+        assert np.allclose(lp.cpu().numpy(), lp_ref, rtol=LOGPOST_TOL, atol=0)
+    lp_f, g_f = vb.vip_grad_logpost(c, grid, geom, x, dobs, case.sigma, **kw, ws_tag="mbf")
+    assert rel(g, g_f.cpu().numpy()) <= 1e-6
+    assert np.allclose(lp.cpu().numpy(), lp_f.cpu().numpy(), rtol=1e-6, atol=0)
+    c.set_tile(-2)
+
+
 def test_rerun_is_bitwise_identical():
     case = build_case(configs.C1)
     c = ctx()

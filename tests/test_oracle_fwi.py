@@ -196,3 +196,41 @@ def test_ricker_closed_form():
     # zero crossings at t0 +- 1 / (pi f sqrt 2)
     tz = 0.15 + 1.0 / (np.pi * 10.0 * np.sqrt(2.0))
     assert abs(ricker_closed_form(np.array([tz]), 10.0, 0.15)[0]) < 1e-15
+
+
+def _minibatch_setup():
+    """Four shots on a small grid (two particles) for the minibatch pins."""
+    grid = fwi.Grid(nz=12, nx=14, nb=6, nt=90, dx=10.0, dz=10.0, dt=1e-3)
+    z = np.arange(12)[:, None]
+    x = np.arange(14)[None, :]
+    v_true = 1900.0 + 35.0 * z + 120.0 * np.exp(-((z - 6) ** 2 + (x - 7) ** 2) / 8.0)
+    geom = fwi.Geometry(src_iz=(1, 1, 2, 1), src_ix=(2, 5, 9, 12), rec_iz=tuple([2] * 14),
+                        rec_ix=tuple(range(14)), f0=30.0)
+    dobs = fwi.simulate(v_true, grid, geom)
+    sigma = 0.05 * float(np.sqrt(np.mean(dobs ** 2)))
+    vels = np.stack([1900.0 + 33.0 * z + 4.0 * np.sin(0.5 * x) + 0 * x,
+                     1950.0 + 30.0 * z + 0 * x])
+    return grid, geom, vels, dobs, sigma
+
+
+def test_minibatch_estimate_is_unbiased_over_all_subsets():
+    """Section 2.4's stochastic gradient from uniformly random shot subsets:
+    the average over every subset of b shots reproduces the full-data
+    log-likelihood and gradient (a wrong scale, or a wrong shot, breaks it)."""
+    import itertools
+    grid, geom, vels, dobs, sigma = _minibatch_setup()
+    lp_full, g_full = fwi.grad_logpost(vels, grid, geom, dobs, sigma)
+    for b in (1, 2, 3):
+        subsets = list(itertools.combinations(range(geom.ns), b))
+        lps, gs = zip(*[fwi.minibatch_grad_logpost(vels, grid, geom, dobs, sigma, s)
+                        for s in subsets])
+        lp_avg, g_avg = np.mean(lps, axis=0), np.mean(gs, axis=0)
+        assert np.allclose(lp_avg, lp_full, rtol=1e-12, atol=0), b
+        assert np.linalg.norm(g_avg - g_full) <= 1e-12 * np.linalg.norm(g_full), b
+    # all shots in another order: the full-data value itself
+    lp_all, g_all = fwi.minibatch_grad_logpost(vels, grid, geom, dobs, sigma, [2, 0, 3, 1])
+    assert np.allclose(lp_all, lp_full, rtol=1e-12, atol=0)
+    assert np.linalg.norm(g_all - g_full) <= 1e-12 * np.linalg.norm(g_full)
+    # one subset is not the full value (the estimate is stochastic)
+    lp_one, _ = fwi.minibatch_grad_logpost(vels, grid, geom, dobs, sigma, [1, 3])
+    assert not np.allclose(lp_one, lp_full, rtol=1e-3)
