@@ -100,16 +100,30 @@ typedef struct {
   int32_t nobs;
 } vip_geometry;
 
-/* Prior (section 3): VIP_PRIOR_NONE, or a uniform prior on [lo, hi] per
- * coordinate applied by strategy 1 -- after an update, values outside the
- * bounds are reset to the nearest bound.  lo, hi: device float [d].  With the
- * uniform prior the log-prior is 0 inside the bounds (normalisation dropped)
- * and its gradient is 0. */
+/* Prior (section 3), per coordinate; all arrays device float [d]:
+ *  VIP_PRIOR_NONE.
+ *  VIP_PRIOR_UNIFORM_CLIP: uniform on [lo, hi] applied by strategy 1 -- after
+ *    an update, values outside the bounds are reset to the nearest bound.  The
+ *    log-prior is 0 inside (normalisation dropped), -inf outside; gradient 0.
+ *  VIP_PRIOR_UNIFORM_TRANSFORM: uniform on [lo, hi] applied by strategy 2 --
+ *    the particles live in the unconstrained space of eq:transform,
+ *    theta = log(m - a) - log(b - m), m = a + (b - a) / (1 + exp(-theta)).
+ *    vip_grad_logpost then takes theta in vel and returns the log-density of
+ *    theta, -J(m) + sum log|dm/dtheta| with dm/dtheta = (m - a)(b - m)/(b - a),
+ *    and its gradient with respect to theta, dlogp/dm dm/dtheta
+ *    + (a + b - 2m)/(b - a); the SVGD steps do not clip.
+ *  VIP_PRIOR_GAUSSIAN: independent normal priors N(mean, std^2): log-prior
+ *    -1/2 sum ((m - mean)/std)^2 (constants dropped), gradient
+ *    -(m - mean)/std^2; the SVGD steps do not clip.
+ * lo, hi are read by the uniform kinds, mean, std by the Gaussian one. */
 #define VIP_PRIOR_NONE 0
 #define VIP_PRIOR_UNIFORM_CLIP 1
+#define VIP_PRIOR_UNIFORM_TRANSFORM 2
+#define VIP_PRIOR_GAUSSIAN 3
 typedef struct {
   int32_t kind;
   const float *lo, *hi;
+  const float *mean, *std;
 } vip_prior;
 
 /* ---- context ------------------------------------------------------------ */
@@ -171,6 +185,13 @@ vip_status vip_poll(vip_ctx *ctx, void *ws, uint32_t *flags);
  * unit-peak Ricker wavelet of section 4.2 (t0 <= 0 selects t0 = 1.5/f0).
  * out: device float [nt]. */
 vip_status vip_ricker(vip_ctx *ctx, int32_t nt, double dt, double f0, double t0, float *out);
+
+/* eq:transform for a VIP_PRIOR_UNIFORM_TRANSFORM prior over n particles of d
+ * coordinates (device [n][d]): direction 0 maps theta -> m, direction 1 maps
+ * m -> theta (m strictly inside (lo, hi); FP64 arithmetic, FP32 out).  in and
+ * out may alias.  VIP_E_ARG for another prior kind. */
+vip_status vip_prior_transform(vip_ctx *ctx, const vip_prior *prior, int32_t n, int64_t d,
+                               const float *in, float *out, int32_t direction);
 
 /* ---- forward modelling ------------------------------------------------- */
 

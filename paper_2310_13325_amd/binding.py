@@ -25,6 +25,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvip.so")
 VIP_OK = 0
 VIP_PRIOR_NONE = 0
 VIP_PRIOR_UNIFORM_CLIP = 1
+VIP_PRIOR_UNIFORM_TRANSFORM = 2
+VIP_PRIOR_GAUSSIAN = 3
 VIP_BW_MEDIAN_ALL = 0
 VIP_BW_MEDIAN_OFFDIAG = 1
 VIP_BW_FIXED = 2
@@ -52,7 +54,8 @@ class VipGeometry(ctypes.Structure):
 
 
 class VipPrior(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p)]
+    _fields_ = [("kind", ctypes.c_int32), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
+                ("mean", ctypes.c_void_p), ("std", ctypes.c_void_p)]
 
 
 class VipSvgdLayout(ctypes.Structure):
@@ -121,6 +124,7 @@ def lib() -> ctypes.CDLL:
             "vip_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "vip_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
             "vip_tile_count": (ctypes.c_int, []),
+            "vip_prior_transform": (ctypes.c_int, [vp, PR, i32, i64, vp, vp, i32]),
             "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
             "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
@@ -217,10 +221,54 @@ class Geometry:
                            p(self.rec_iz), w, si, self.nobs)
 
 
-def _prior(lo: Optional[torch.Tensor], hi: Optional[torch.Tensor]):
+@dataclass
+class Prior:
+    """A prior of section 3 (device float [d] arrays): uniform on [lo, hi] by
+    clipping (strategy 1) or in the transformed space of eq:transform
+    (strategy 2), or independent Gaussians N(mean, std^2)."""
+    kind: int
+    lo: Optional[torch.Tensor] = None
+    hi: Optional[torch.Tensor] = None
+    mean: Optional[torch.Tensor] = None
+    std: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def clip(lo, hi):
+        return Prior(VIP_PRIOR_UNIFORM_CLIP, lo=lo, hi=hi)
+
+    @staticmethod
+    def transform(lo, hi):
+        return Prior(VIP_PRIOR_UNIFORM_TRANSFORM, lo=lo, hi=hi)
+
+    @staticmethod
+    def gaussian(mean, std):
+        return Prior(VIP_PRIOR_GAUSSIAN, mean=mean, std=std)
+
+    def c(self) -> VipPrior:
+        f = lambda t: _ptr(t.reshape(-1), torch.float32) if t is not None else None
+        return VipPrior(self.kind, f(self.lo), f(self.hi), f(self.mean), f(self.std))
+
+
+def _prior(lo: Optional[torch.Tensor], hi: Optional[torch.Tensor], prior: Optional[Prior] = None):
+    if prior is not None:
+        return prior.c()
     if lo is None:
         return None
     return VipPrior(VIP_PRIOR_UNIFORM_CLIP, _ptr(lo, torch.float32), _ptr(hi, torch.float32))
+
+
+def vip_prior_transform(ctx: "Context", prior: Prior, x: torch.Tensor, to_theta: bool,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """eq:transform over particles x [n][...]: m -> theta (to_theta) or theta -> m."""
+    ctx.sync_stream()
+    n = x.shape[0]
+    d = x.numel() // n
+    out = torch.empty_like(x) if out is None else out
+    pr = prior.c()
+    _check(lib().vip_prior_transform(ctx.handle, ctypes.byref(pr), n, d, _ptr(x, torch.float32),
+                                     _ptr(out, torch.float32), 1 if to_theta else 0),
+           "vip_prior_transform")
+    return out
 
 
 def _ptr(t: Optional[torch.Tensor], dtype=None):
@@ -384,7 +432,7 @@ def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor
                      lo: Optional[torch.Tensor] = None, hi: Optional[torch.Tensor] = None,
                      live_pairs: int = 0, logpost: Optional[torch.Tensor] = None,
                      grad: Optional[torch.Tensor] = None, ws_tag: str = "grad",
-                     stored_steps: int = 0):
+                     stored_steps: int = 0, prior: Optional[Prior] = None):
     ctx.sync_stream()
     npart = vel.shape[0]
     nbytes = grad_logpost_workspace_bytes(grid, geom, npart, ckpt_every, live_pairs,
@@ -395,7 +443,7 @@ def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor
     if grad is None:
         grad = torch.empty_like(vel)
     g, ge = grid.c(), geom.c()
-    pr = _prior(lo, hi)
+    pr = _prior(lo, hi, prior)
     _check(lib().vip_grad_logpost(ctx.handle, ctypes.byref(g), ctypes.byref(ge),
                                   ctypes.byref(pr) if pr is not None else None, npart,
                                   _ptr(vel, torch.float32), _ptr(dobs, torch.float32), sigma,
@@ -417,7 +465,8 @@ def vip_grad_logpost_minibatch(ctx: Context, grid: Grid, geom: Geometry, vel: to
 
 
 def vip_grad_logpost_plain(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
-                           dobs: torch.Tensor, sigma: float, lo=None, hi=None):
+                           dobs: torch.Tensor, sigma: float, lo=None, hi=None,
+                           prior: Optional[Prior] = None):
     ctx.sync_stream()
     npart = vel.shape[0]
     g, ge = grid.c(), geom.c()
@@ -428,7 +477,7 @@ def vip_grad_logpost_plain(ctx: Context, grid: Grid, geom: Geometry, vel: torch.
     ws = ctx.workspace("plain", nbytes.value)
     logpost = torch.empty(npart, dtype=torch.float64, device=ctx.device)
     grad = torch.empty_like(vel)
-    pr = _prior(lo, hi)
+    pr = _prior(lo, hi, prior)
     _check(lib().vip_grad_logpost_plain(ctx.handle, ctypes.byref(g), ctypes.byref(ge),
                                         ctypes.byref(pr) if pr is not None else None, npart,
                                         _ptr(vel, torch.float32), _ptr(dobs, torch.float32),
@@ -491,13 +540,14 @@ def svgd_layout(n: int, d: int) -> VipSvgdLayout:
 def vip_svgd_step(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
                   bw_mode: int = VIP_BW_MEDIAN_ALL, h_fixed: float = 1.0,
                   gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
-                  h2_out: Optional[torch.Tensor] = None, ws_tag: str = "svgd") -> torch.Tensor:
+                  h2_out: Optional[torch.Tensor] = None, ws_tag: str = "svgd",
+                  prior: Optional[Prior] = None) -> torch.Tensor:
     """In-place SVGD update of x ([n][d] float32); returns the workspace."""
     ctx.sync_stream()
     n = x.shape[0]
     d = x.numel() // n
     ws = ctx.workspace(ws_tag, svgd_workspace_bytes(n, d))
-    pr = _prior(lo, hi)
+    pr = _prior(lo, hi, prior)
     _check(lib().vip_svgd_step(ctx.handle, n, d, _ptr(x, torch.float32), _ptr(g, torch.float32),
                                eps, bw_mode, h_fixed, gram_prec,
                                ctypes.byref(pr) if pr is not None else None,
@@ -510,13 +560,14 @@ def vip_ssvgd_step(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
                    xi: Optional[torch.Tensor] = None, seed: int = 0, stream: int = 0,
                    bw_mode: int = VIP_BW_MEDIAN_ALL, h_fixed: float = 1.0,
                    gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
-                   h2_out: Optional[torch.Tensor] = None, ws_tag: str = "svgd") -> torch.Tensor:
+                   h2_out: Optional[torch.Tensor] = None, ws_tag: str = "svgd",
+                   prior: Optional[Prior] = None) -> torch.Tensor:
     """In-place sSVGD update of x; returns the workspace."""
     ctx.sync_stream()
     n = x.shape[0]
     d = x.numel() // n
     ws = ctx.workspace(ws_tag, svgd_workspace_bytes(n, d))
-    pr = _prior(lo, hi)
+    pr = _prior(lo, hi, prior)
     _check(lib().vip_ssvgd_step(ctx.handle, n, d, _ptr(x, torch.float32), _ptr(g, torch.float32),
                                 eps, bw_mode, h_fixed, gram_prec,
                                 ctypes.byref(pr) if pr is not None else None,
@@ -576,13 +627,14 @@ class Problem:
     hi: Optional[torch.Tensor] = None
     logpost: Optional[torch.Tensor] = None
     grad: Optional[torch.Tensor] = None
+    prior: Optional[Prior] = None
 
     def c(self) -> VipProblem:
         if self.logpost is None:
             self.logpost = torch.empty(self.vel.shape[0], dtype=torch.float64, device=self.vel.device)
         if self.grad is None:
             self.grad = torch.empty_like(self.vel)
-        pr = _prior(self.lo, self.hi) or VipPrior(VIP_PRIOR_NONE, None, None)
+        pr = _prior(self.lo, self.hi, self.prior) or VipPrior(VIP_PRIOR_NONE)
         return VipProblem(self.grid.c(), self.geom.c(), pr, self.vel.shape[0],
                           _ptr(self.vel, torch.float32), _ptr(self.dobs, torch.float32), self.sigma,
                           _ptr(self.logpost, torch.float64), _ptr(self.grad, torch.float32))
@@ -625,7 +677,7 @@ def _ensembles(xs, gs, eps, lo, hi, xis, h2s):
         n = x.shape[0]
         pr = _prior(lo[k], hi[k]) if lo is not None else None
         out.append(VipEnsemble(n, x.numel() // n, _ptr(x, torch.float32), _ptr(g, torch.float32),
-                               float(eps[k]), pr or VipPrior(VIP_PRIOR_NONE, None, None),
+                               float(eps[k]), pr or VipPrior(VIP_PRIOR_NONE),
                                _ptr(xis[k], torch.float32) if xis is not None else None,
                                _ptr(h2s[k], torch.float64) if h2s is not None else None))
     return (VipEnsemble * len(out))(*out)

@@ -251,30 +251,82 @@ __global__ void finalize_grad_kernel(const double *acc64, const float *vel, floa
 }
 
 // logpost[p] = -sum_s J[p][s] + log prior (0 inside a uniform box, -inf outside)
+// Prior terms, FP64 per coordinate (section 3, eq:transform).  For the
+// transform kind t is theta and s = 1 / (1 + exp(-theta)): m = a + (b - a) s,
+// log|dm/dtheta| = log(b - a) + log s + log(1 - s), d/dtheta of it = 1 - 2 s.
+__device__ __forceinline__ double softplus(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+__device__ __forceinline__ double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// logpost[p] = -sum_s J[p][s] + log prior; vel holds what the caller passed
+// (theta for the transform kind), model the velocities the sweeps used.
 __global__ __launch_bounds__(256) void logpost_kernel(const double *J, const float *vel,
-                                                      const float *lo, const float *hi, int ns,
+                                                      const float *model, int kind,
+                                                      const float *lo, const float *hi,
+                                                      const float *mean, const float *sd, int ns,
                                                       long long d, double *logpost,
                                                       uint32_t *status) {
+  __shared__ double part[4];
   __shared__ int outside_s;
   const int p = blockIdx.x;
   if (threadIdx.x == 0) outside_s = 0;
   __syncthreads();
-  if (lo) {
-    int out = 0;
-    for (long long e = threadIdx.x; e < d; e += 256) {
-      float v = vel[(long long)p * d + e];
+  double acc = 0.0;
+  int out = 0;
+  for (long long e = threadIdx.x; e < d; e += 256) {
+    const long long i = (long long)p * d + e;
+    if (kind == VIP_PRIOR_UNIFORM_CLIP) {
+      const float v = model[i];
       out |= !(v >= lo[e] && v <= hi[e]);
+    } else if (kind == VIP_PRIOR_UNIFORM_TRANSFORM) {
+      const double t = double(vel[i]);
+      acc += log(double(hi[e]) - double(lo[e])) - softplus(-t) - softplus(t);
+    } else if (kind == VIP_PRIOR_GAUSSIAN) {
+      const double z = (double(model[i]) - double(mean[e])) / double(sd[e]);
+      acc -= 0.5 * z * z;
     }
-    if (out) atomicOr(&outside_s, 1);
   }
+  if (out) atomicOr(&outside_s, 1);
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     double j = 0.0;
     for (int s = 0; s < ns; ++s) j += J[(long long)p * ns + s];
-    double lp = -j;
+    double lp = -j + ((part[0] + part[1]) + (part[2] + part[3]));
     if (outside_s) lp = -INFINITY;
     if (!isfinite(j)) atomicOr(status, VIP_FLAG_NONFINITE);
     logpost[p] = lp;
+  }
+}
+
+// m = a + (b - a) / (1 + exp(-theta)) (direction 0) or theta = log(m - a) -
+// log(b - m) (direction 1), elementwise over [n][d].
+__global__ void prior_transform_kernel(const float *in, float *out, const float *lo,
+                                       const float *hi, long long total, long long d,
+                                       int direction) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long e = i % d;
+  const double a = lo[e], b = hi[e], x = in[i];
+  out[i] = direction == 0 ? float(a + (b - a) * sigmoid(x)) : float(log(x - a) - log(b - x));
+}
+
+// Gradient of the prior terms, in place on grad = d(-J)/dm: the transform
+// kind maps it to theta, dlogp/dm dm/dtheta + (1 - 2 s); the Gaussian kind
+// adds -(m - mean) / std^2.
+__global__ void prior_grad_kernel(float *grad, const float *vel, const float *model, int kind,
+                                  const float *lo, const float *hi, const float *mean,
+                                  const float *sd, long long total, long long d) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long e = i % d;
+  if (kind == VIP_PRIOR_UNIFORM_TRANSFORM) {
+    const double sg = sigmoid(double(vel[i]));
+    grad[i] = float(double(grad[i]) * (double(hi[e]) - double(lo[e])) * sg * (1.0 - sg) +
+                    (1.0 - 2.0 * sg));
+  } else if (kind == VIP_PRIOR_GAUSSIAN) {
+    const double sd2 = double(sd[e]) * double(sd[e]);
+    grad[i] = float(double(grad[i]) - (double(model[i]) - double(mean[e])) / sd2);
   }
 }
 
@@ -814,15 +866,39 @@ vip_status launch_finalize(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, con
   return VIP_OK;
 }
 
-vip_status launch_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
-                          const vip_prior *prior, double *logpost) {
-  const float *lo = nullptr, *hi = nullptr;
-  if (prior && prior->kind == VIP_PRIOR_UNIFORM_CLIP) {
-    lo = prior->lo;
-    hi = prior->hi;
+vip_status check_prior(const vip_prior *prior) {
+  if (!prior || prior->kind == VIP_PRIOR_NONE) return VIP_OK;
+  switch (prior->kind) {
+    case VIP_PRIOR_UNIFORM_CLIP:
+    case VIP_PRIOR_UNIFORM_TRANSFORM: return (prior->lo && prior->hi) ? VIP_OK : VIP_E_ARG;
+    case VIP_PRIOR_GAUSSIAN: return (prior->mean && prior->std) ? VIP_OK : VIP_E_ARG;
+    default: return VIP_E_ARG;
   }
-  logpost_kernel<<<dim3(D.np), dim3(256), 0, ctx->s()>>>(P.J, vel, lo, hi, D.ns,
-                                                         (long long)D.nx * D.nz, logpost, P.status);
+}
+
+const float *prior_model(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
+                         const vip_prior *prior) {
+  if (!prior || prior->kind != VIP_PRIOR_UNIFORM_TRANSFORM) return vel;
+  const long long d = (long long)D.nx * D.nz, total = d * D.np;
+  prior_transform_kernel<<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, ctx->s()>>>(
+      vel, P.model, prior->lo, prior->hi, total, d, 0);
+  return P.model;
+}
+
+vip_status launch_prior_and_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+                                    const float *vel, const float *model, const vip_prior *prior,
+                                    float *grad, double *logpost) {
+  VIP_LAUNCH_CHECK();
+  const int kind = prior ? prior->kind : VIP_PRIOR_NONE;
+  const long long d = (long long)D.nx * D.nz, total = d * D.np;
+  if (kind == VIP_PRIOR_UNIFORM_TRANSFORM || kind == VIP_PRIOR_GAUSSIAN) {
+    prior_grad_kernel<<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, ctx->s()>>>(
+        grad, vel, model, kind, prior->lo, prior->hi, prior->mean, prior->std, total, d);
+    VIP_LAUNCH_CHECK();
+  }
+  logpost_kernel<<<dim3(D.np), dim3(256), 0, ctx->s()>>>(
+      P.J, vel, model, kind, prior ? prior->lo : nullptr, prior ? prior->hi : nullptr,
+      prior ? prior->mean : nullptr, prior ? prior->std : nullptr, D.ns, d, logpost, P.status);
   VIP_LAUNCH_CHECK();
   return VIP_OK;
 }
@@ -951,9 +1027,7 @@ vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
                             float *grad, void *ws, size_t ws_bytes) {
   if (!ctx || !vel || !dobs || !logpost || !grad || !ws) return VIP_E_ARG;
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return VIP_E_ARG;
-  if (prior && prior->kind != VIP_PRIOR_NONE &&
-      (prior->kind != VIP_PRIOR_UNIFORM_CLIP || !prior->lo || !prior->hi))
-    return VIP_E_ARG;
+  VIP_TRY(check_prior(prior));
   FwiDims D;
   VIP_TRY(make_dims(grid, geom, np, ckpt_every, live_pairs, true, &D, stored_steps));
   apply_tile_choice(ctx, &D);
@@ -966,12 +1040,14 @@ vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
       .add(stored_steps)
       .add(live_pairs).add(logpost).add(grad).add(ws).add(geom->wavelet).add(geom->ns)
       .add(geom->nr);
-  kb.add(prior ? prior->kind : -1).add(prior ? prior->lo : nullptr).add(prior ? prior->hi : nullptr);
+  kb.add(prior ? prior->kind : -1).add(prior ? prior->lo : nullptr).add(prior ? prior->hi : nullptr)
+      .add(prior ? prior->mean : nullptr).add(prior ? prior->std : nullptr);
   kb.add_array(geom->src_ix, geom->ns).add_array(geom->src_iz, geom->ns)
       .add_array(geom->rec_ix, geom->nr).add_array(geom->rec_iz, geom->nr);
   return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
     VIP_TRY(upload_tables(ctx, D, grid, geom, P));
-    VIP_TRY(launch_coeff(ctx, D, grid, vel, P));
+    const float *model = prior_model(ctx, D, P, vel, prior);
+    VIP_TRY(launch_coeff(ctx, D, grid, model, P));
     VIP_TRY(fill_f64(ctx->s(), P.acc64, size_t(D.pairs * D.N), 0.0));
     for (long long p0 = 0; p0 < D.pairs; p0 += D.live) {
       int cnt = int(std::min<long long>(D.live, D.pairs - p0));
@@ -980,8 +1056,8 @@ vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
       VIP_TRY(backward_sweep(ctx, D, P, geom->wavelet, int(p0), cnt, P.resid, P.ckpt,
                              P.acc64 + p0 * D.N));
     }
-    VIP_TRY(launch_finalize(ctx, D, P, vel, grad, -1.0f));
-    return launch_logpost(ctx, D, P, vel, prior, logpost);
+    VIP_TRY(launch_finalize(ctx, D, P, model, grad, -1.0f));
+    return launch_prior_and_logpost(ctx, D, P, vel, model, prior, grad, logpost);
   });
 }
 
@@ -1067,9 +1143,7 @@ vip_status vip_grad_logpost_multi(vip_ctx *ctx, int32_t nprob, const vip_problem
     const vip_problem &q = probs[p];
     if (!q.vel || !q.dobs || !q.logpost || !q.grad) return VIP_E_ARG;
     if (!(q.sigma > 0.0) || !std::isfinite(q.sigma)) return VIP_E_ARG;
-    if (q.prior.kind != VIP_PRIOR_NONE &&
-        (q.prior.kind != VIP_PRIOR_UNIFORM_CLIP || !q.prior.lo || !q.prior.hi))
-      return VIP_E_ARG;
+    VIP_TRY(check_prior(&q.prior));
   }
   const int cfg = ctx->tile >= 0 ? ctx->tile : default_tile_multi(Ds);
   if (ctx->tile == -1) return VIP_E_UNSUPPORTED;   // batching needs a blocked tile shape
@@ -1083,18 +1157,21 @@ vip_status vip_grad_logpost_multi(vip_ctx *ctx, int32_t nprob, const vip_problem
   for (int p = 0; p < nprob; ++p) {
     const vip_problem &q = probs[p];
     kb.add(q.grid).add(q.np).add(q.vel).add(q.dobs).add(q.sigma).add(q.logpost).add(q.grad)
-        .add(q.prior.kind).add(q.prior.lo).add(q.prior.hi).add(q.geom.wavelet).add(q.geom.ns)
+        .add(q.prior.kind).add(q.prior.lo).add(q.prior.hi).add(q.prior.mean).add(q.prior.std)
+        .add(q.geom.wavelet).add(q.geom.ns)
         .add(q.geom.nr);
     kb.add_array(q.geom.src_ix, q.geom.ns).add_array(q.geom.src_iz, q.geom.ns)
         .add_array(q.geom.rec_ix, q.geom.nr).add_array(q.geom.rec_iz, q.geom.nr);
   }
   return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
     std::vector<std::vector<std::pair<int, BlockArgs>>> fwd(nprob), bwd(nprob);
+    std::vector<const float *> models(nprob);
     for (int p = 0; p < nprob; ++p) {
       const FwiDims &D = Ds[p];
       const FwiPlan &P = Ps[p];
       VIP_TRY(upload_tables(ctx, D, &probs[p].grid, &probs[p].geom, P));
-      VIP_TRY(launch_coeff(ctx, D, &probs[p].grid, probs[p].vel, P));
+      models[p] = prior_model(ctx, D, P, probs[p].vel, &probs[p].prior);
+      VIP_TRY(launch_coeff(ctx, D, &probs[p].grid, models[p], P));
       VIP_TRY(fill_f64(ctx->s(), P.acc64, size_t(D.pairs * D.N), 0.0));
       const Emitter ef{ctx, cfg, int(D.pairs), &fwd[p]};
       VIP_TRY(forward_sweep_blocked(ef, D, P, probs[p].geom.wavelet, 0, int(D.pairs), P.resid, P.ckpt));
@@ -1107,11 +1184,25 @@ vip_status vip_grad_logpost_multi(vip_ctx *ctx, int32_t nprob, const vip_problem
       VIP_TRY(launch_residual(ctx, Ds[p], Ps[p], 0, int(Ds[p].pairs), probs[p].dobs, probs[p].sigma));
     VIP_TRY(launch_merged(ctx, cfg, bwd));
     for (int p = 0; p < nprob; ++p) {
-      VIP_TRY(launch_finalize(ctx, Ds[p], Ps[p], probs[p].vel, probs[p].grad, -1.0f));
-      VIP_TRY(launch_logpost(ctx, Ds[p], Ps[p], probs[p].vel, &probs[p].prior, probs[p].logpost));
+      VIP_TRY(launch_finalize(ctx, Ds[p], Ps[p], models[p], probs[p].grad, -1.0f));
+      VIP_TRY(launch_prior_and_logpost(ctx, Ds[p], Ps[p], probs[p].vel, models[p], &probs[p].prior,
+                                       probs[p].grad, probs[p].logpost));
     }
     return VIP_OK;
   });
+}
+
+vip_status vip_prior_transform(vip_ctx *ctx, const vip_prior *prior, int32_t n, int64_t d,
+                               const float *in, float *out, int32_t direction) {
+  if (!ctx || !prior || !in || !out || n < 1 || d < 1 || (direction != 0 && direction != 1))
+    return VIP_E_ARG;
+  if (prior->kind != VIP_PRIOR_UNIFORM_TRANSFORM || !prior->lo || !prior->hi) return VIP_E_ARG;
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  const long long total = (long long)n * d;
+  prior_transform_kernel<<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, ctx->user>>>(
+      in, out, prior->lo, prior->hi, total, d, direction);
+  VIP_LAUNCH_CHECK();
+  return VIP_OK;
 }
 
 }  // extern "C"

@@ -136,6 +136,7 @@ struct FwiPlan {
   double *acc64 = nullptr;
   float *resid = nullptr;
   double *J = nullptr;
+  float *model = nullptr;   // velocities from theta (transform prior) [np][nz][nx]
   float *hist = nullptr;    // plain path: full a-history of one pair
   size_t bytes = 0;
 };
@@ -170,6 +171,7 @@ inline void plan_fwi(const FwiDims &D, char *base, int kind, FwiPlan *P) {
     P->acc32 = A.take<float>(field);
     P->resid = A.take<float>(size_t(live) * D.nt * D.nr);
     P->J = A.take<double>(D.pairs);
+    P->model = A.take<float>(size_t(D.np) * D.nx * D.nz);
   } else if (kind == PLAN_TAPE) {
     P->seg = A.take<float>(size_t(live) * size_t(D.seg_slots) * D.N);
     P->acc32 = A.take<float>(field);
@@ -178,6 +180,7 @@ inline void plan_fwi(const FwiDims &D, char *base, int kind, FwiPlan *P) {
     P->resid = A.take<float>(size_t(D.nt) * D.nr);
     P->J = A.take<double>(D.pairs);
     P->acc32 = A.take<float>(D.N);
+    P->model = A.take<float>(size_t(D.np) * D.nx * D.nz);
   }
   P->bytes = A.bytes();
 }
@@ -194,7 +197,14 @@ vip_status launch_coeff(vip_ctx *ctx, const FwiDims &D, const vip_grid *grid, co
                         const FwiPlan &P);
 vip_status launch_finalize(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
                            float *grad, float sign);
-vip_status launch_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
-                          const vip_prior *prior, double *logpost);
+vip_status check_prior(const vip_prior *prior);
+// theta -> m into the plan's model buffer for the transform prior (returns the
+// velocities the sweeps use: vel itself for the other kinds)
+const float *prior_model(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, const float *vel,
+                         const vip_prior *prior);
+// prior terms of the gradient (in place, after the misfit gradient) and logpost
+vip_status launch_prior_and_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P,
+                                    const float *vel, const float *model, const vip_prior *prior,
+                                    float *grad, double *logpost);
 
 }  // namespace vip

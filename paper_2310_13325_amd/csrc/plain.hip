@@ -84,9 +84,7 @@ vip_status vip_grad_logpost_plain(vip_ctx *ctx, const vip_grid *grid, const vip_
                                   void *ws, size_t ws_bytes) {
   if (!ctx || !vel || !dobs || !logpost || !grad || !ws) return VIP_E_ARG;
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return VIP_E_ARG;
-  if (prior && prior->kind != VIP_PRIOR_NONE &&
-      (prior->kind != VIP_PRIOR_UNIFORM_CLIP || !prior->lo || !prior->hi))
-    return VIP_E_ARG;
+  VIP_TRY(check_prior(prior));
   FwiDims D;
   VIP_TRY(make_dims(grid, geom, np, grid->nt, 1, true, &D));
   FwiPlan P;
@@ -104,7 +102,8 @@ vip_status vip_grad_logpost_plain(vip_ctx *ctx, const vip_grid *grid, const vip_
       nodes[r] = (geom->rec_iz[r] + D.nb) * D.NX + geom->rec_ix[r] + D.nb;
     VIP_TRY(upload_i32(s, rec_node, nodes.data(), nodes.size()));
   }
-  VIP_TRY(launch_coeff(ctx, D, grid, vel, P));
+  const float *model = prior_model(ctx, D, P, vel, prior);
+  VIP_TRY(launch_coeff(ctx, D, grid, model, P));
   const int N = int(D.N);
   const dim3 gN((N + 255) / 256), b256(256), gR((D.nr + 255) / 256);
   for (long long pair = 0; pair < D.pairs; ++pair) {
@@ -142,8 +141,8 @@ vip_status vip_grad_logpost_plain(vip_ctx *ctx, const vip_grid *grid, const vip_
       VIP_LAUNCH_CHECK();
     }
   }
-  VIP_TRY(launch_finalize(ctx, D, P, vel, grad, -1.0f));
-  return launch_logpost(ctx, D, P, vel, prior, logpost);
+  VIP_TRY(launch_finalize(ctx, D, P, model, grad, -1.0f));
+  return launch_prior_and_logpost(ctx, D, P, vel, model, prior, grad, logpost);
 }
 
 }  // extern "C"

@@ -5,7 +5,8 @@
 //                                   = 1/n [ (K G)_i + (s_i x_i - (K X)_i) / h^2 ],  s_i = sum_j K_ij
 //   sSVGD (eq:stochastic_svgd, eq:matrixDK, eq:noise_term)
 //                             x_i <- x_i + eps phi_i + sqrt(2 eps) (L Xi)_i,  L L^T = K / n
-//   uniform prior, strategy 1 (section 3): clip to [lo, hi] after the update.
+//   uniform prior, strategy 1 (section 3): clip to [lo, hi] after the update
+//   (the other prior kinds act through the gradient only).
 //
 // Kernel sequence for one step:
 //   centre      xbar = mean_i x_i (FP64 sums); Xc = X - xbar in FP32 and BF16
@@ -616,9 +617,15 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   if (gram_prec != VIP_GRAM_BF16 && gram_prec != VIP_GRAM_FP32) return VIP_E_ARG;
   const float *lo = nullptr, *hi = nullptr;
   if (prior && prior->kind != VIP_PRIOR_NONE) {
-    if (prior->kind != VIP_PRIOR_UNIFORM_CLIP || !prior->lo || !prior->hi) return VIP_E_ARG;
-    lo = prior->lo;
-    hi = prior->hi;
+    // only the clip strategy acts on the update; the transform and Gaussian
+    // priors enter through the gradient
+    if (prior->kind == VIP_PRIOR_UNIFORM_CLIP) {
+      if (!prior->lo || !prior->hi) return VIP_E_ARG;
+      lo = prior->lo;
+      hi = prior->hi;
+    } else if (prior->kind != VIP_PRIOR_UNIFORM_TRANSFORM && prior->kind != VIP_PRIOR_GAUSSIAN) {
+      return VIP_E_ARG;
+    }
   }
   if (noise && n > kCholMax) return VIP_E_UNSUPPORTED;
   SvgdPlan P;
