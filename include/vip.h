@@ -339,6 +339,36 @@ vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const flo
                          int32_t bw_mode, double h_fixed, int32_t gram_prec,
                          const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes);
 
+/* Step rules for the SVGD update (the optimisers section 2.2 lists for
+ * gradient ascent: SGD, AdaGrad, AdaDelta, Adam), applied per coordinate to
+ * the direction phi in place of x <- x + eps phi:
+ *   SGD       x += eps phi
+ *   AdaGrad   s1 += phi^2;                      x += eps phi / (sqrt(s1) + delta)
+ *   AdaDelta  s1 = rho s1 + (1 - rho) phi^2;    u = sqrt(s2 + delta) / sqrt(s1 + delta) phi;
+ *             s2 = rho s2 + (1 - rho) u^2;      x += eps u          (rho = beta1; eps = 1 is
+ *                                                                    the rule as published)
+ *   Adam      s1 = b1 s1 + (1 - b1) phi;  s2 = b2 s2 + (1 - b2) phi^2;
+ *             x += eps (s1 / (1 - b1^t)) / (sqrt(s2 / (1 - b2^t)) + delta)
+ * s1, s2: device float [n][d] state owned by the caller, zero before the first
+ * step and carried from step to step (NULL where the rule needs none); t: the
+ * 1-based number of this step.  The prior is applied after the step as in
+ * vip_svgd_step.  (The sSVGD step keeps its plain form: its noise scale is
+ * tied to eps.) */
+#define VIP_OPT_SGD 0
+#define VIP_OPT_ADAGRAD 1
+#define VIP_OPT_ADADELTA 2
+#define VIP_OPT_ADAM 3
+typedef struct {
+  int32_t kind;
+  float *s1, *s2;
+  int64_t t;
+  double beta1, beta2, delta;
+} vip_optimizer;
+vip_status vip_svgd_step_opt(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                             double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                             const vip_prior *prior, const vip_optimizer *opt, double *h2_out,
+                             void *ws, size_t ws_bytes);
+
 /* One stochastic SVGD iteration (eq:stochastic_svgd): the SVGD direction plus
  * noise eta = sqrt(2 eps) L xi per coordinate, L the lower Cholesky factor of
  * K/n (eq:matrixDK, eq:noise_term; factorised in FP64 on the device, with

@@ -71,6 +71,15 @@ class VipTiming(ctypes.Structure):
                 ("point_steps", ctypes.c_double * 4)]
 
 
+class VipOptimizer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("s1", ctypes.c_void_p), ("s2", ctypes.c_void_p),
+                ("t", ctypes.c_int64), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("delta", ctypes.c_double)]
+
+
+VIP_OPT_SGD, VIP_OPT_ADAGRAD, VIP_OPT_ADADELTA, VIP_OPT_ADAM = range(4)
+
+
 class VipError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -125,6 +134,8 @@ def lib() -> ctypes.CDLL:
             "vip_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
             "vip_tile_count": (ctypes.c_int, []),
             "vip_prior_transform": (ctypes.c_int, [vp, PR, i32, i64, vp, vp, i32]),
+            "vip_svgd_step_opt": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR,
+                                                 ctypes.POINTER(VipOptimizer), vp, vp, sz]),
             "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
             "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
@@ -553,6 +564,43 @@ def vip_svgd_step(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
                                ctypes.byref(pr) if pr is not None else None,
                                _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
                                ws.numel()), "vip_svgd_step")
+    return ws
+
+
+class Optimizer:
+    """State of a step rule for vip_svgd_step_opt (zero-initialised, carried
+    from step to step)."""
+
+    def __init__(self, kind: int, like: torch.Tensor, beta1: float = 0.9, beta2: float = 0.999,
+                 delta: float = 1e-8):
+        self.kind, self.beta1, self.beta2, self.delta = kind, beta1, beta2, delta
+        self.t = 0
+        self.s1 = torch.zeros_like(like) if kind != VIP_OPT_SGD else None
+        self.s2 = torch.zeros_like(like) if kind in (VIP_OPT_ADADELTA, VIP_OPT_ADAM) else None
+
+    def c(self) -> VipOptimizer:
+        return VipOptimizer(self.kind, _ptr(self.s1, torch.float32), _ptr(self.s2, torch.float32),
+                            self.t, self.beta1, self.beta2, self.delta)
+
+
+def vip_svgd_step_opt(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float, opt: Optimizer,
+                      bw_mode: int = VIP_BW_MEDIAN_ALL, h_fixed: float = 1.0,
+                      gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
+                      prior: Optional[Prior] = None, h2_out: Optional[torch.Tensor] = None,
+                      ws_tag: str = "svgd") -> torch.Tensor:
+    """In-place SVGD update of x with the step rule `opt` (its step count advances)."""
+    ctx.sync_stream()
+    n = x.shape[0]
+    d = x.numel() // n
+    ws = ctx.workspace(ws_tag, svgd_workspace_bytes(n, d))
+    pr = _prior(lo, hi, prior)
+    opt.t += 1
+    oc = opt.c()
+    _check(lib().vip_svgd_step_opt(ctx.handle, n, d, _ptr(x, torch.float32),
+                                   _ptr(g, torch.float32), eps, bw_mode, h_fixed, gram_prec,
+                                   ctypes.byref(pr) if pr is not None else None, ctypes.byref(oc),
+                                   _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel()), "vip_svgd_step_opt")
     return ws
 
 

@@ -494,6 +494,40 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
+// Step rule applied to the direction phi of one coordinate (SGD, AdaGrad,
+// AdaDelta, Adam; state s1, s2 per coordinate, FP32).
+struct OptArgs {
+  int kind;
+  float *s1, *s2;
+  float b1, b2, delta;
+  float c1, c2;   // Adam bias corrections 1 / (1 - b1^t), 1 / (1 - b2^t)
+};
+__device__ __forceinline__ float opt_step(const OptArgs &o, long long e, float p, float eps) {
+  switch (o.kind) {
+    case VIP_OPT_ADAGRAD: {
+      const float G = o.s1[e] + p * p;
+      o.s1[e] = G;
+      return eps * p / (sqrtf(G) + o.delta);
+    }
+    case VIP_OPT_ADADELTA: {
+      const float Eg = o.b1 * o.s1[e] + (1.0f - o.b1) * p * p;
+      const float Ed = o.s2[e];
+      const float u = sqrtf(Ed + o.delta) / sqrtf(Eg + o.delta) * p;
+      o.s1[e] = Eg;
+      o.s2[e] = o.b1 * Ed + (1.0f - o.b1) * u * u;
+      return eps * u;
+    }
+    case VIP_OPT_ADAM: {
+      const float mo = o.b1 * o.s1[e] + (1.0f - o.b1) * p;
+      const float ve = o.b2 * o.s2[e] + (1.0f - o.b2) * p * p;
+      o.s1[e] = mo;
+      o.s2[e] = ve;
+      return eps * (mo * o.c1) / (sqrtf(ve * o.c2) + o.delta);
+    }
+    default: return eps * p;
+  }
+}
+
 // The same update (without noise) with the product on the FP32 matrix cores
 // (v_mfma_f32_32x32x2_f32: lane l holds A[l % 32][l / 32] and B[l / 32][l % 32];
 // result register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]).
@@ -510,7 +544,7 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
                                                          const double *h2, float *x, float *phi,
                                                          const float *lo, const float *hi, int n,
                                                          long long d, int mblocks, int vec,
-                                                         float eps, uint32_t *status) {
+                                                         float eps, OptArgs opt, uint32_t *status) {
   __shared__ __attribute__((aligned(16))) float As[UK][UM + UP];   // As[k][i] = K[i][j0 + k]
   __shared__ __attribute__((aligned(16))) float Bs[UK][UN + UP];   // Bs[k][a] = B[j0 + k][a0 + a]
   // tile index, contiguous per XCD (blocks are dealt round-robin over 8 XCDs)
@@ -594,7 +628,7 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
         const long long e = (long long)i * d + a;
         const float p = fmaf(si, xc[e], acc[m][q][r]) * inv_n;
         phi[e] = p;
-        float v = x[e] + eps * p;
+        float v = x[e] + opt_step(opt, e, p, eps);
         if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
         bad |= !isfinite(v);
         x[e] = v;
@@ -609,8 +643,30 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                               double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
                               const vip_prior *prior, bool noise, const float *xi, uint64_t seed,
                               uint64_t stream, double *h2_out, void *ws, size_t ws_bytes,
-                              uint32_t *status_ptr = nullptr) {
+                              uint32_t *status_ptr = nullptr,
+                              const vip_optimizer *opt = nullptr) {
   if (!ctx || !x || !g || !ws) return VIP_E_ARG;
+  OptArgs oa{VIP_OPT_SGD, nullptr, nullptr, 0.f, 0.f, 0.f, 1.f, 1.f};
+  if (opt) {
+    if (noise) return VIP_E_ARG;
+    if (opt->kind < VIP_OPT_SGD || opt->kind > VIP_OPT_ADAM) return VIP_E_ARG;
+    const bool two = opt->kind == VIP_OPT_ADADELTA || opt->kind == VIP_OPT_ADAM;
+    if (opt->kind != VIP_OPT_SGD && (!opt->s1 || (two && !opt->s2))) return VIP_E_ARG;
+    if (opt->kind == VIP_OPT_ADAM && opt->t < 1) return VIP_E_ARG;
+    if (!(opt->delta >= 0.0) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
+        !(opt->beta2 >= 0.0 && opt->beta2 < 1.0))
+      return VIP_E_ARG;
+    oa.kind = opt->kind;
+    oa.s1 = opt->s1;
+    oa.s2 = opt->s2;
+    oa.b1 = float(opt->beta1);
+    oa.b2 = float(opt->beta2);
+    oa.delta = float(opt->delta);
+    if (opt->kind == VIP_OPT_ADAM) {
+      oa.c1 = float(1.0 / (1.0 - std::pow(opt->beta1, double(opt->t))));
+      oa.c2 = float(1.0 / (1.0 - std::pow(opt->beta2, double(opt->t))));
+    }
+  }
   if (n < 1 || d < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return VIP_E_ARG;
   if (bw_mode < VIP_BW_MEDIAN_ALL || bw_mode > VIP_BW_FIXED) return VIP_E_ARG;
   if (bw_mode == VIP_BW_FIXED && !(h_fixed > 0.0)) return VIP_E_ARG;
@@ -703,7 +759,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                     (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
     update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
-        P.K, g, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), P.status);
+        P.K, g, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa, P.status);
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;
@@ -742,6 +798,15 @@ vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const flo
                          const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes) {
   return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr, 0, 0,
                      h2_out, ws, ws_bytes);
+}
+
+vip_status vip_svgd_step_opt(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                             double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                             const vip_prior *prior, const vip_optimizer *opt, double *h2_out,
+                             void *ws, size_t ws_bytes) {
+  if (!opt) return VIP_E_ARG;
+  return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr, 0, 0,
+                     h2_out, ws, ws_bytes, nullptr, opt);
 }
 
 }  // extern "C"

@@ -180,3 +180,31 @@ def test_philox_words_bitwise_and_normals():
     z = vb.vip_philox_normals(c, 4003, seed, stream).cpu().numpy()
     zr = ophilox.normals(4003, seed, stream)
     assert np.abs(z - zr).max() <= 2e-5
+
+
+@pytest.mark.parametrize("kind", [vb.VIP_OPT_SGD, vb.VIP_OPT_ADAGRAD, vb.VIP_OPT_ADADELTA,
+                                  vb.VIP_OPT_ADAM])
+def test_svgd_step_rules_match_oracle_over_three_steps(kind):
+    """SGD / AdaGrad / AdaDelta / Adam on the SVGD direction: three steps with
+    the state carried, against the FP64 oracle fed the same directions."""
+    from oracle import optim
+    n, d = 40, 777
+    # centred particles and step scales giving displacements of ~10, far above
+    # the FP32 spacing of x, so the displacement read back from x is exact enough
+    X, G = _ensemble(n, d, 91, base=0.0)
+    c = ctx()
+    x, g = dev(X), dev(G)
+    b1 = 0.95 if kind == vb.VIP_OPT_ADADELTA else 0.9
+    eps = {vb.VIP_OPT_SGD: 2000.0, vb.VIP_OPT_ADAGRAD: 10.0, vb.VIP_OPT_ADADELTA: 5000.0,
+           vb.VIP_OPT_ADAM: 10.0}[kind]
+    opt = vb.Optimizer(kind, x, beta1=b1, beta2=0.999, delta=1e-6)
+    Xr, st = X.copy(), {}
+    for it in range(3):
+        vb.vip_svgd_step_opt(c, x, g, eps, opt, gram_prec=vb.VIP_GRAM_FP32)
+        phi = osvgd.svgd_direction(Xr, G)["phi"]
+        Xr = Xr + optim.step(kind, phi, st, eps, b1, 0.999, 1e-6)
+        e = rel(x.cpu().numpy() - X, Xr - X)
+        print(f"step rule {kind} step {it}: displacement rel L2 {e:.2e}", flush=True)
+        assert e <= 1e-4
+    if kind != vb.VIP_OPT_SGD:
+        assert rel(opt.s1.cpu().numpy(), st["s1"]) <= 1e-4
