@@ -335,6 +335,17 @@ def main():
                 vb.vip_svgd_step(ctx, Xw, Gc, case.eps, gram_prec=prec, ws_tag="c5")
             torch.cuda.synchronize()
             svgd[name] = round(reps / (time.perf_counter() - t), 2)
+        # the diagonal matrix-valued kernel (Q = 1 / per-coordinate variance), BF16 Gram
+        Xw = Xc.clone()
+        diag = lambda: vb.vip_svgd_step_ex(ctx, Xw, Gc, case.eps, kernel=vb.VIP_KERNEL_DIAG_VAR,
+                                           gram_prec=vb.VIP_GRAM_BF16, ws_tag="c5")
+        diag()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            diag()
+        torch.cuda.synchronize()
+        svgd["bf16_gram_diag_kernel"] = round(reps / (time.perf_counter() - t), 2)
         extra["svgd_steps_per_s"] = {"n": case.n, "d": case.d, **svgd}
         log(f"svgd c5: {svgd}")
         ctx._ws.pop("c5", None)

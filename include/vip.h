@@ -369,6 +369,34 @@ vip_status vip_svgd_step_opt(vip_ctx *ctx, int32_t n, int64_t d, float *x, const
                              const vip_prior *prior, const vip_optimizer *opt, double *h2_out,
                              void *ws, size_t ws_bytes);
 
+/* Kernel of the SVGD / sSVGD steps (section 5): the RBF of eq:rbf, or the
+ * diagonal matrix-valued kernel that combines a positive definite diagonal
+ * Q with the RBF, Q = inverse per-coordinate variance across the particles
+ * (recomputed at every step, ddof 0; q_a = 1 where the variance is 0):
+ * K(m, m') = Q^-1 exp(-(m - m')^T Q (m - m') / (2 h^2)).  Its direction is
+ *   phi_i = 1/n sum_j k_ij [Q^-1 g_j + (x_i - x_j) / h^2],
+ * the median bandwidth taken on the Q-weighted distances, and the sSVGD
+ * noise is sqrt(2 eps) L Xi Q^-1/2. */
+#define VIP_KERNEL_RBF 0
+#define VIP_KERNEL_DIAG_VAR 1
+
+/* One SVGD (noise = 0) or sSVGD (noise = 1) step with every option: bandwidth
+ * mode and fixed h, Gram precision, kernel, the sSVGD normals (xi, or Philox
+ * seed/stream when xi is NULL) and a step rule (SVGD only; NULL = SGD). */
+typedef struct {
+  int32_t bw_mode;
+  double h_fixed;
+  int32_t gram_prec;
+  int32_t kernel;
+  int32_t noise;
+  const float *xi;
+  uint64_t seed, stream;
+  const vip_optimizer *opt;
+} vip_svgd_config;
+vip_status vip_svgd_step_ex(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                            double eps, const vip_svgd_config *cfg, const vip_prior *prior,
+                            double *h2_out, void *ws, size_t ws_bytes);
+
 /* One stochastic SVGD iteration (eq:stochastic_svgd): the SVGD direction plus
  * noise eta = sqrt(2 eps) L xi per coordinate, L the lower Cholesky factor of
  * K/n (eq:matrixDK, eq:noise_term; factorised in FP64 on the device, with

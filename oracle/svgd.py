@@ -16,6 +16,14 @@ Paper basis (VIP, section 2.3-2.4):
   * section 4       posterior mean / std over final particles (SVGD) or over
                     retained post-burn-in samples (sSVGD).
 
+  * section 5        diagonal matrix-valued kernel: a positive definite diagonal
+                    Q combined with the RBF, Q = inverse per-coordinate variance
+                    across particles; read as K(m, m') = Q^-1 k_Q(m, m') with
+                    k_Q = exp(-(m - m')^T Q (m - m') / (2 h^2)), whose SVGD
+                    direction is 1/n sum_j k_Q(m_j, m_i) [Q^-1 grad log p(m_j)
+                    + (m_i - m_j) / h^2] (the divergence of Q^-1 k_Q brings
+                    Q^-1 Q = I), and whose sSVGD noise is sqrt(2 eps) L Xi Q^-1/2.
+
 Readings where the paper is silent:
   * bandwidth: median heuristic over all n^2 squared distances (the n zero
     self-distances included; even count -> mean of the two middle values),
@@ -23,7 +31,9 @@ Readings where the paper is silent:
   * the j = i term of eq:phi_mean is kept (k_ii = 1, its gradient is 0);
   * Cholesky failure: add jitter 1e-12 * trace(A)/n, times 10 per retry, at
     most 6 retries;
-  * std uses ddof = 0.
+  * std uses ddof = 0;
+  * Q of the matrix-valued kernel: q_a = 1 / var_a over the current particles
+    (ddof = 0), q_a = 1 where var_a = 0; recomputed at every step.
 """
 from __future__ import annotations
 
@@ -76,6 +86,73 @@ def bandwidth_sq(D: np.ndarray, mode: int = BW_MEDIAN_ALL, h_fixed: float = 1.0)
 def rbf(D: np.ndarray, h2: float) -> np.ndarray:
     """eq:rbf on precomputed squared distances."""
     return np.exp(-D / (2.0 * h2))
+
+
+def diag_precision(X):
+    """q_a = 1 / var_a across the particles (ddof = 0); 1 where var_a = 0."""
+    X = np.asarray(X, dtype=np.float64)
+    var = X.var(axis=0, ddof=0)
+    return np.where(var > 0.0, 1.0 / np.where(var > 0.0, var, 1.0), 1.0)
+
+
+def sqdist_q(X, q):
+    """D_ij = sum_a q_a (x_ia - x_ja)^2, evaluated directly."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    D = np.empty((n, n))
+    for i in range(n):
+        diff = X - X[i]
+        D[i] = (diff * diff) @ q
+    return D
+
+
+def svgd_direction_diag(X, G, q, mode=BW_MEDIAN_ALL, h_fixed=1.0):
+    """Diagonal matrix-valued kernel (see the header):
+    phi_i = 1/n [ sum_j K_ij g_j / q + (s_i x_i - sum_j K_ij x_j) / h^2 ],
+    K_ij = exp(-D^Q_ij / (2 h^2)).  Returns dict(D, h2, K, s, phi)."""
+    X = np.asarray(X, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    n = X.shape[0]
+    D = sqdist_q(X, q)
+    h2 = bandwidth_sq(D, mode, h_fixed)
+    K = rbf(D, h2)
+    s = K.sum(axis=1)
+    phi = (K @ (G / q) + (s[:, None] * X - K @ X) / h2) / n
+    return {"D": D, "h2": h2, "K": K, "s": s, "phi": phi}
+
+
+def svgd_direction_diag_bruteforce(X, G, q, h2):
+    """The matrix-valued-kernel direction as a literal double loop."""
+    X = np.asarray(X, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    n, d = X.shape
+    phi = np.zeros((n, d))
+    for i in range(n):
+        acc = np.zeros(d)
+        for j in range(n):
+            diff = X[i] - X[j]
+            k = np.exp(-float(diff @ (q * diff)) / (2.0 * h2))
+            acc += k * (G[j] / q) + k * diff / h2
+        phi[i] = acc / n
+    return phi
+
+
+def svgd_step_diag(X, G, eps, lo=None, hi=None, mode=BW_MEDIAN_ALL, h_fixed=1.0):
+    """One SVGD iteration with the diagonal matrix-valued kernel, Q from X."""
+    q = diag_precision(X)
+    info = svgd_direction_diag(X, G, q, mode, h_fixed)
+    info["q"] = q
+    return clip(np.asarray(X, dtype=np.float64) + eps * info["phi"], lo, hi), info
+
+
+def ssvgd_step_diag(X, G, eps, xi, lo=None, hi=None, mode=BW_MEDIAN_ALL, h_fixed=1.0):
+    """sSVGD with the diagonal matrix-valued kernel: noise sqrt(2 eps) L Xi / sqrt(q)."""
+    q = diag_precision(X)
+    info = svgd_direction_diag(X, G, q, mode, h_fixed)
+    eta, L, retries = ssvgd_noise(info["K"], eps, xi)
+    eta = eta / np.sqrt(q)
+    info.update(q=q, eta=eta, L=L, retries=retries)
+    return clip(np.asarray(X, dtype=np.float64) + eps * info["phi"] + eta, lo, hi), info
 
 
 def svgd_direction(X, G, mode=BW_MEDIAN_ALL, h_fixed=1.0, D=None):

@@ -78,6 +78,14 @@ class VipOptimizer(ctypes.Structure):
 
 
 VIP_OPT_SGD, VIP_OPT_ADAGRAD, VIP_OPT_ADADELTA, VIP_OPT_ADAM = range(4)
+VIP_KERNEL_RBF, VIP_KERNEL_DIAG_VAR = 0, 1
+
+
+class VipSvgdConfig(ctypes.Structure):
+    _fields_ = [("bw_mode", ctypes.c_int32), ("h_fixed", ctypes.c_double),
+                ("gram_prec", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("noise", ctypes.c_int32), ("xi", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_uint64), ("opt", ctypes.POINTER(VipOptimizer))]
 
 
 class VipError(RuntimeError):
@@ -136,6 +144,8 @@ def lib() -> ctypes.CDLL:
             "vip_prior_transform": (ctypes.c_int, [vp, PR, i32, i64, vp, vp, i32]),
             "vip_svgd_step_opt": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR,
                                                  ctypes.POINTER(VipOptimizer), vp, vp, sz]),
+            "vip_svgd_step_ex": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl,
+                                                ctypes.POINTER(VipSvgdConfig), PR, vp, vp, sz]),
             "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
             "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
@@ -601,6 +611,34 @@ def vip_svgd_step_opt(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float
                                    ctypes.byref(pr) if pr is not None else None, ctypes.byref(oc),
                                    _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
                                    ws.numel()), "vip_svgd_step_opt")
+    return ws
+
+
+def vip_svgd_step_ex(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
+                     kernel: int = VIP_KERNEL_RBF, noise: bool = False,
+                     xi: Optional[torch.Tensor] = None, seed: int = 0, stream: int = 0,
+                     opt: Optional[Optimizer] = None, bw_mode: int = VIP_BW_MEDIAN_ALL,
+                     h_fixed: float = 1.0, gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
+                     prior: Optional[Prior] = None, h2_out: Optional[torch.Tensor] = None,
+                     ws_tag: str = "svgd") -> torch.Tensor:
+    """In-place SVGD / sSVGD update with every option (kernel, noise, step rule)."""
+    ctx.sync_stream()
+    n = x.shape[0]
+    d = x.numel() // n
+    ws = ctx.workspace(ws_tag, svgd_workspace_bytes(n, d))
+    pr = _prior(lo, hi, prior)
+    oc = None
+    if opt is not None:
+        opt.t += 1
+        oc = opt.c()
+    cfg = VipSvgdConfig(bw_mode, h_fixed, gram_prec, kernel, 1 if noise else 0,
+                        _ptr(xi, torch.float32), seed, stream,
+                        ctypes.pointer(oc) if oc is not None else None)
+    _check(lib().vip_svgd_step_ex(ctx.handle, n, d, _ptr(x, torch.float32), _ptr(g, torch.float32),
+                                  eps, ctypes.byref(cfg),
+                                  ctypes.byref(pr) if pr is not None else None,
+                                  _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel()), "vip_svgd_step_ex")
     return ws
 
 

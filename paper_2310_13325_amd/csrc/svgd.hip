@@ -45,12 +45,16 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 // ---- centre ----------------------------------------------------------------
 // Block of 64 coordinates x 16 row groups: each thread sums every 16th
 // particle of its coordinate (FP64), the 16 partial sums are added in a fixed
-// order, and the block then writes the centred columns.
+// order, and the block then writes the centred columns.  For the diagonal
+// matrix-valued kernel (sq != null) a second pass forms the variance across
+// particles (FP64, ddof 0), q = 1 / var (1 where var = 0), and the BF16 copy
+// used by the Gram is scaled by sqrt(q).
 constexpr int CENTRE_COLS = 64, CENTRE_GROUPS = 16;
 __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
-    const float *x, float *xbar, float *xc, uint16_t *xc16, int n, long long d, uint32_t *status) {
+    const float *x, float *xbar, float *xc, uint16_t *xc16, float *sq, float *vq, int n,
+    long long d, uint32_t *status) {
   __shared__ double part[CENTRE_GROUPS][CENTRE_COLS];
-  __shared__ float mean[CENTRE_COLS];
+  __shared__ float mean[CENTRE_COLS], scale[CENTRE_COLS];
   const int tx = threadIdx.x % CENTRE_COLS, ty = threadIdx.x / CENTRE_COLS;
   const long long a = (long long)blockIdx.x * CENTRE_COLS + tx;
   const bool in = a < d;
@@ -64,19 +68,42 @@ __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
     for (int g = 0; g < CENTRE_GROUPS; ++g) t += part[g][tx];
     const float m = float(t / double(n));
     mean[tx] = m;
+    scale[tx] = 1.0f;
     if (in) {
       xbar[a] = m;
       if (!isfinite(m)) atomicOr(status, VIP_FLAG_NONFINITE);
     }
   }
   __syncthreads();
-  if (!in) return;
   const float m = mean[tx];
+  if (sq) {
+    double ss = 0.0;
+    if (in)
+      for (int i = ty; i < n; i += CENTRE_GROUPS) {
+        const double v = double(x[(long long)i * d + a]) - double(m);
+        ss += v * v;
+      }
+    __syncthreads();   // every thread has read the means and sums before part is reused
+    part[ty][tx] = ss;
+    __syncthreads();
+    if (ty == 0 && in) {
+      double t = 0.0;
+      for (int g = 0; g < CENTRE_GROUPS; ++g) t += part[g][tx];
+      const double var = t / double(n);
+      const double qv = var > 0.0 ? 1.0 / var : 1.0;
+      scale[tx] = float(sqrt(qv));
+      sq[a] = float(sqrt(qv));
+      vq[a] = float(1.0 / qv);
+    }
+    __syncthreads();
+  }
+  if (!in) return;
+  const float sc = scale[tx];
   for (int i = ty; i < n; i += CENTRE_GROUPS) {
     const long long e = (long long)i * d + a;
     const float v = x[e] - m;
     xc[e] = v;
-    xc16[e] = f32_to_bf16_rne(v);
+    xc16[e] = f32_to_bf16_rne(sq ? v * sc : v);
   }
 }
 
@@ -174,8 +201,9 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, fl
 // r % 4][l % 32]).  k is staged 16 at a time, stored k-major in LDS so that
 // each half-wave reads 32 consecutive rows.
 constexpr int GF_K = 16, GF_P = 4;
-__global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, float *part, int n,
-                                                       long long d, long long kspan, int nbt) {
+__global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, const float *sq,
+                                                       float *part, int n, long long d,
+                                                       long long kspan, int nbt) {
   __shared__ __attribute__((aligned(16))) float As[GF_K][GB + GF_P];
   __shared__ __attribute__((aligned(16))) float Bs[GF_K][GB + GF_P];
   const int nup = nbt * (nbt + 1) / 2;
@@ -212,6 +240,12 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, float *p
           vb[c] = (j0 + row < n && k + c < k1) ? xc[(long long)(j0 + row) * d + k + c] : 0.0f;
         }
       }
+      if (sq)   // diagonal kernel: columns scaled by sqrt(q)
+        for (int c = 0; c < 4; ++c) {
+          const float w = k + c < k1 ? sq[k + c] : 0.0f;
+          va[c] *= w;
+          vb[c] *= w;
+        }
       for (int c = 0; c < 4; ++c) {
         As[kq + c][row] = va[c];
         Bs[kq + c][row] = vb[c];
@@ -422,7 +456,8 @@ __global__ void philox_fill_kernel(float *out, long long count, uint32_t k0, uin
 template <bool NOISE>
 __global__ __launch_bounds__(256) void update_kernel(const float *K, const float *Lf,
                                                      const float *g, const float *xc,
-                                                     const float *xi, const float *s,
+                                                     const float *vq, const float *xi,
+                                                     const float *s,
                                                      const double *h2, float *x, float *phi,
                                                      const float *lo, const float *hi, int n,
                                                      long long d, float eps, float noise_scale,
@@ -449,7 +484,7 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
       int jr = idx >> 6, ac = idx & 63;   // 16 j x 64 coordinates
       bool okb = (j0 + jr < n) && (a0 + ac < d);
       long long src = (long long)(j0 + jr) * d + a0 + ac;
-      Bb[jr][ac] = okb ? fmaf(-xc[src], inv_h2, g[src]) : 0.0f;
+      Bb[jr][ac] = okb ? fmaf(-xc[src], inv_h2, vq ? g[src] * vq[a0 + ac] : g[src]) : 0.0f;
       if (NOISE) Bz[jr][ac] = okb ? xi[src] : 0.0f;
     }
     __syncthreads();
@@ -485,7 +520,7 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
       float p = fmaf(si, xc[e], kb[r][c]) * inv_n;
       phi[e] = p;
       float v = x[e] + eps * p;
-      if (NOISE) v += noise_scale * lz[r][c];
+      if (NOISE) v += (vq ? noise_scale * sqrtf(vq[a]) : noise_scale) * lz[r][c];
       if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
       bad |= !isfinite(v);
       x[e] = v;
@@ -540,7 +575,8 @@ __device__ __forceinline__ float opt_step(const OptArgs &o, long long e, float p
 // meet in one L2.
 constexpr int UM = 256, UN = 128, UK = 16, UP = 4, UT = 512;
 __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const float *g,
-                                                         const float *xc, const float *s,
+                                                         const float *xc, const float *vq,
+                                                         const float *s,
                                                          const double *h2, float *x, float *phi,
                                                          const float *lo, const float *hi, int n,
                                                          long long d, int mblocks, int vec,
@@ -580,6 +616,13 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
     if (j < n) {
       pg = load4(g + (long long)j * d, a0 + bc, d);
       px = load4(xc + (long long)j * d, a0 + bc, d);
+      if (vq) {   // diagonal kernel: Q^-1 g
+        const float4 w = load4(vq, a0 + bc, d);
+        pg.x *= w.x;
+        pg.y *= w.y;
+        pg.z *= w.z;
+        pg.w *= w.w;
+      }
     }
   };
   auto store_stage = [&]() {
@@ -644,8 +687,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                               const vip_prior *prior, bool noise, const float *xi, uint64_t seed,
                               uint64_t stream, double *h2_out, void *ws, size_t ws_bytes,
                               uint32_t *status_ptr = nullptr,
-                              const vip_optimizer *opt = nullptr) {
+                              const vip_optimizer *opt = nullptr, int32_t kernel = VIP_KERNEL_RBF) {
   if (!ctx || !x || !g || !ws) return VIP_E_ARG;
+  if (kernel != VIP_KERNEL_RBF && kernel != VIP_KERNEL_DIAG_VAR) return VIP_E_ARG;
   OptArgs oa{VIP_OPT_SGD, nullptr, nullptr, 0.f, 0.f, 0.f, 1.f, 1.f};
   if (opt) {
     if (noise) return VIP_E_ARG;
@@ -694,16 +738,18 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   const long long nn = (long long)n * n;
   const unsigned nn_blocks = unsigned((nn + 255) / 256);
 
+  const bool diag = kernel == VIP_KERNEL_DIAG_VAR;
+  float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
   centre_kernel<<<dim3(unsigned((d + CENTRE_COLS - 1) / CENTRE_COLS)),
-                  dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(x, P.xbar, P.xc, P.xc16, n, d,
-                                                             P.status);
+                  dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(x, P.xbar, P.xc, P.xc16, sq, vq, n,
+                                                             d, P.status);
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;
   dim3 ggrid(unsigned(nup * P.splits));
   if (gram_prec == VIP_GRAM_BF16)
     gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan, P.nbt);
   else
-    gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, P.part, n, d, P.kspan, P.nbt);
+    gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, sq, P.part, n, d, P.kspan, P.nbt);
   VIP_LAUNCH_CHECK();
   gram_reduce_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.part, P.G, n, P.splits);
   VIP_LAUNCH_CHECK();
@@ -747,7 +793,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       VIP_LAUNCH_CHECK();
       xin = P.xi;
     }
-    update_kernel<true><<<ugrid, dim3(256), 0, s>>>(P.K, P.Lf, g, P.xc, xin, P.s, P.h2, x, P.phi,
+    update_kernel<true><<<ugrid, dim3(256), 0, s>>>(P.K, P.Lf, g, P.xc, vq, xin, P.s, P.h2, x, P.phi,
                                                     lo, hi, n, d, float(eps),
                                                     float(std::sqrt(2.0 * eps)), P.status);
   } else {
@@ -759,7 +805,8 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                     (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
     update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
-        P.K, g, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa, P.status);
+        P.K, g, P.xc, vq, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa,
+        P.status);
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;
@@ -798,6 +845,16 @@ vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const flo
                          const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes) {
   return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr, 0, 0,
                      h2_out, ws, ws_bytes);
+}
+
+vip_status vip_svgd_step_ex(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                            double eps, const vip_svgd_config *cfg, const vip_prior *prior,
+                            double *h2_out, void *ws, size_t ws_bytes) {
+  if (!cfg) return VIP_E_ARG;
+  if (cfg->noise != 0 && cfg->noise != 1) return VIP_E_ARG;
+  return svgd_common(ctx, n, d, x, g, eps, cfg->bw_mode, cfg->h_fixed, cfg->gram_prec, prior,
+                     cfg->noise != 0, cfg->xi, cfg->seed, cfg->stream, h2_out, ws, ws_bytes,
+                     nullptr, cfg->opt, cfg->kernel);
 }
 
 vip_status vip_svgd_step_opt(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,

@@ -11,6 +11,7 @@ namespace vip {
 struct SvgdPlan {
   uint32_t *status = nullptr;
   float *xbar = nullptr, *xc = nullptr;
+  float *sq = nullptr, *vq = nullptr;   // diagonal kernel: sqrt(q_a), 1 / q_a per coordinate
   uint16_t *xc16 = nullptr;
   float *part = nullptr, *G = nullptr, *D = nullptr, *K = nullptr, *s = nullptr;
   uint32_t *hist = nullptr, *sel = nullptr;
@@ -37,6 +38,8 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   A.base = base;
   P->status = reinterpret_cast<uint32_t *>(base);
   P->xbar = A.take<float>(size_t(d));
+  P->sq = A.take<float>(size_t(d));
+  P->vq = A.take<float>(size_t(d));
   P->xc = A.take<float>(nd);
   P->xc16 = A.take<uint16_t>(nd);
   P->part = A.take<float>(size_t(P->splits) * nn);

@@ -208,3 +208,43 @@ def test_svgd_step_rules_match_oracle_over_three_steps(kind):
         assert e <= 1e-4
     if kind != vb.VIP_OPT_SGD:
         assert rel(opt.s1.cpu().numpy(), st["s1"]) <= 1e-4
+
+
+@pytest.mark.parametrize("gram,n,d", [(vb.VIP_GRAM_FP32, 64, 1000), (vb.VIP_GRAM_FP32, 130, 515),
+                                      (vb.VIP_GRAM_BF16, 300, 4100)])
+def test_diag_matrix_kernel_svgd_matches_oracle(gram, n, d):
+    """Diagonal matrix-valued kernel (Q = 1 / per-coordinate variance): the
+    Q-weighted distances, the median bandwidth on them, Q^-1 on the gradients."""
+    r = np.random.default_rng(n + d)
+    scales = np.float32(np.exp(r.uniform(-2.0, 3.0, d))).astype(np.float64)
+    X = np.float32(100.0 * r.standard_normal((n, d)) * scales).astype(np.float64)
+    G = np.float32(-X / (100.0 * scales) ** 2 + 0.01 * r.standard_normal((n, d)) / scales
+                   ).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    eps = 50.0
+    ws = vb.vip_svgd_step_ex(c, x, dev(G), eps, kernel=vb.VIP_KERNEL_DIAG_VAR, gram_prec=gram)
+    D, K, h2, phi, _ = _inspect(ws, n, d)
+    Xr, info = osvgd.svgd_step_diag(X, G, eps)
+    tol = dict(D=1e-5, phi=1e-4) if gram == vb.VIP_GRAM_FP32 else dict(D=2e-4, phi=2e-3)
+    errs = dict(D=rel(D, info["D"]), K=rel(K, info["K"]), phi=rel(phi, info["phi"]),
+                X=rel(x.cpu().numpy() - X, Xr - X))
+    print(f"diag kernel gram={gram} n={n} d={d}: {errs}", flush=True)
+    assert errs["D"] <= tol["D"] and errs["phi"] <= tol["phi"] and errs["X"] <= tol["phi"]
+
+
+def test_diag_matrix_kernel_ssvgd_matches_oracle():
+    n, d, eps = 24, 3001, 20.0
+    r = np.random.default_rng(41)
+    scales = np.float32(np.exp(r.uniform(-1.0, 2.0, d))).astype(np.float64)
+    X = np.float32(3000.0 + 100.0 * r.standard_normal((n, d)) * scales).astype(np.float64)
+    G = np.float32(-(X - 3000.0) / (100.0 * scales) ** 2).astype(np.float64)
+    xi = np.float32(r.standard_normal((n, d))).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    vb.vip_svgd_step_ex(c, x, dev(G), eps, kernel=vb.VIP_KERNEL_DIAG_VAR, noise=True, xi=dev(xi),
+                        gram_prec=vb.VIP_GRAM_FP32)
+    Xr, info = osvgd.ssvgd_step_diag(X, G, eps, xi)
+    e = rel(x.cpu().numpy() - X, Xr - X)
+    print(f"diag kernel sSVGD: displacement rel L2 {e:.2e}", flush=True)
+    assert e <= 1e-4
