@@ -28,6 +28,7 @@ up to whatever constant the caller's log p drops.
 from __future__ import annotations
 
 import numpy as np
+from scipy.linalg import solve_triangular
 
 from oracle import optim
 
@@ -56,7 +57,10 @@ def gradients(L, eta, g, family=FULL_RANK):
     S = eta.shape[0]
     Lm = np.tril(_as_L(L, family))
     grad_mu = g.mean(axis=0)
-    full = g.T @ eta / S + np.linalg.inv(Lm).T
+    # L^-1 by triangular solve: it is exactly lower triangular, where a
+    # general pivoted inverse leaks rounding into the structural zeros
+    Linv = solve_triangular(Lm, np.eye(Lm.shape[0]), lower=True)
+    full = g.T @ eta / S + Linv.T
     if family == MEAN_FIELD:
         return grad_mu, np.diag(full).copy()
     return grad_mu, np.tril(full)

@@ -170,3 +170,15 @@ def test_sgd_step_moves_by_eps_times_the_gradient_and_keeps_l_lower():
     assert np.allclose(mu2, mu + 0.25 * g.mean(axis=0), rtol=1e-14)
     assert np.allclose(L2 - L, 0.25 * gL, rtol=1e-12, atol=1e-14)
     assert np.all(np.triu(L2, 1) == 0.0)
+
+
+def test_inverse_term_keeps_its_structural_zeros_for_ill_conditioned_factors():
+    """The lower part of (L^-1)^T is diag(1 / L_ii) however badly L is
+    conditioned (a random triangular factor of this size has entries of L^-1
+    near 1e13)."""
+    r = np.random.default_rng(18)
+    d = 400
+    L = np.tril(r.normal(0.0, 0.3, (d, d)), -1) + np.diag(r.uniform(0.5, 2.0, d))
+    zero = np.zeros((1, d))
+    _, gL = advi.gradients(L, zero, zero)
+    assert np.array_equal(gL, np.diag(1.0 / np.diag(L)))
