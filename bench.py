@@ -135,6 +135,67 @@ def cpu_baseline(prob, S, ctx, vb, torch, workers):
     return base, err
 
 
+def advi_rates(prob, S, ctx, vb, torch, sched):
+    """ADVI (section 2.2) on the same posterior in the unconstrained space of
+    eq:transform, from N(0, I) as in section 4.1, one Monte Carlo sample per
+    iteration (Table 1 counts one simulation per ADVI iteration) and eight:
+    whole iterations per second (normals, sample, gradients, Adam step) for
+    both families, and the HBM rate of the two full-rank kernels that stream
+    the d(d+1)/2 entries of L (the sample reads 4 B per entry, the Adam step
+    reads and writes L and two state arrays, 24 B per entry)."""
+    prior = vb.Prior.transform(S["lo"], S["hi"])
+    d = prob.d
+    out = {"d": d, "prior": "uniform, transformed (eq:transform)", "rule": "adam",
+           "eps": 1e-3}
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for label, family, nsamp in (("full_rank_S1", vb.VIP_ADVI_FULL_RANK, 1),
+                                 ("full_rank_S8", vb.VIP_ADVI_FULL_RANK, 8),
+                                 ("mean_field_S1", vb.VIP_ADVI_MEAN_FIELD, 1)):
+        q = vb.Advi(d, family, kind=vb.VIP_OPT_ADAM)
+        it = lambda k: vb.vip_advi_iteration(ctx, q, S["grid"], S["geom"], S["dobs"], S["sigma"],
+                                             prior, nsamp, 1e-3, seed=2310, it=k,
+                                             ckpt_every=prob.ckpt_every,
+                                             stored_steps=sched["stored_steps"], ws_tag="advi")
+        it(0)
+        torch.cuda.synchronize()
+        reps = 5
+        t = time.perf_counter()
+        for k in range(reps):
+            elbo = it(1 + k)
+        torch.cuda.synchronize()
+        rate = reps / (time.perf_counter() - t)
+        out[label] = {"iterations_per_s": round(rate, 3),
+                      "simulations_per_s": round(rate * nsamp, 3),
+                      "elbo_last": float(elbo.item())}
+        if label == "full_rank_S8":
+            # the two full-rank kernels alone, HIP events on the context stream
+            eta = vb.vip_philox_normals(ctx, nsamp * d, 7, 0).view(nsamp, d)
+            g = 1e-3 * vb.vip_philox_normals(ctx, nsamp * d, 7, 1).view(nsamp, d)
+            entries = d * (d + 1) / 2
+            for kname, call, bpe in (
+                    ("advi_sample_full", lambda: vb.vip_advi_sample(ctx, q, eta), 4.0),
+                    ("advi_step_full_adam", lambda: vb.vip_advi_step(ctx, q, eta, g, 0.0), 24.0)):
+                call()
+                a, b = ev(), ev()
+                n = 10
+                a.record()
+                for _ in range(n):
+                    call()
+                b.record()
+                torch.cuda.synchronize()
+                us = a.elapsed_time(b) * 1e3 / n
+                gbs = bpe * entries / (us * 1e-6) / 1e9
+                out[label][kname] = {"avg_launch_us": round(us, 1),
+                                     "alg_bytes_per_launch": int(bpe * entries),
+                                     "alg_GBps": round(gbs, 1),
+                                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                     "samples": nsamp}
+        del q
+        ctx._ws.pop("advi", None)
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +206,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-minibatch", action="store_true")
+    ap.add_argument("--no-advi", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the gradient through a hipGraph")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile shape (no tile tuning)")
     ap.add_argument("--stored-steps", type=int, default=None,
@@ -305,6 +367,9 @@ def main():
                               "vs_full": round(rate / value, 2)}
         ctx._ws.pop("minibatch", None)
         log(f"minibatch {b} of {prob.ns} shots: {rate:.1f} estimates/s")
+    if not args.no_advi:
+        extra["advi"] = advi_rates(prob, S, ctx, vb, torch, sched)
+        log(f"advi: {extra['advi']}")
     if not args.no_plain:
         x1 = S["x"][:1].contiguous()
         vb.vip_grad_logpost_plain(ctx, S["grid"], S["geom"], x1, S["dobs"], S["sigma"],

@@ -429,6 +429,56 @@ vip_status vip_ssvgd_step_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *
                                 int32_t bw_mode, double h_fixed, int32_t gram_prec, uint64_t seed,
                                 uint64_t stream, void *ws, size_t ws_bytes);
 
+/* Automatic differentiation variational inference (section 2.2: eq:normal,
+ * eq:argmaxELBO_advi, eq:gradient_mu, eq:gradient_L; the mean-field family of
+ * section 5).  The variational family is q(theta) = N(mu, L L^T) in the
+ * unconstrained space theta = T(m) of eq:transform; the per-sample gradients
+ * g_s = grad_theta log p(theta_s, d) that the step consumes are what
+ * vip_grad_logpost returns for the samples theta_s under the
+ * VIP_PRIOR_UNIFORM_TRANSFORM prior (or the Gaussian prior, T = identity;
+ * the clip prior has no place in ADVI).  An iteration is: draw eta
+ * (vip_philox_normals), vip_advi_sample, vip_grad_logpost on the S samples,
+ * vip_advi_step.
+ *  family VIP_ADVI_FULL_RANK: L is device float [d][ldl], row-major, ldl >= d,
+ *    lower triangular; only entries j <= i are read or written (the rest of
+ *    the array is never touched).
+ *  family VIP_ADVI_MEAN_FIELD: L is device float [d], the diagonal of a
+ *    diagonal L (ldl is ignored).
+ * mu: device float [d].  eta, theta, g: device float [S][d], S the number of
+ * Monte Carlo samples, 1 <= S <= VIP_ADVI_MAX_SAMPLES.  No call allocates or
+ * synchronises; VIP_E_ARG for a bad family, size or pointer. */
+#define VIP_ADVI_FULL_RANK 0
+#define VIP_ADVI_MEAN_FIELD 1
+#define VIP_ADVI_MAX_SAMPLES 32
+
+/* theta[s] = mu + L eta[s] for every sample s (FP32 arithmetic; the full-rank
+ * product sums in a fixed order, so results are reproducible). */
+vip_status vip_advi_sample(vip_ctx *ctx, int32_t family, int64_t d, int32_t S, const float *mu,
+                           const float *L, int64_t ldl, const float *eta, float *theta);
+
+/* One ascent step of the ELBO from the samples of vip_advi_sample (same mu, L,
+ * eta) and their gradients g:
+ *   grad_mu = 1/S sum_s g[s]                                  (eq:gradient_mu)
+ *   grad_L  = 1/S sum_s g[s] eta[s]^T + (L^-1)^T              (eq:gradient_L)
+ * on the free entries (the lower triangle, or the diagonal for the mean
+ * field; the lower part of (L^-1)^T is diag(1 / L_ii)), then
+ *   mu += rule(grad_mu),  L += rule(grad_L)
+ * with the step rules of vip_svgd_step_opt (eps and the rule's formula as
+ * there; NULL = SGD).  opt_mu's state arrays are device float [d]; opt_L's
+ * have L's layout ([d][ldl] with the same ldl, or [d]); each is zero before
+ * the first step.  The diagonal of L must be nonzero.
+ * grad_mu ([d]) and grad_L (L's layout, lower entries only): device float
+ * outputs of the two gradients, or NULL.
+ * elbo: device double [1] or NULL; when given, logpost (device double [S],
+ * the samples' log p(theta_s, d) from vip_grad_logpost) is required and
+ *   elbo = 1/S sum_s logpost[s] + sum_i log|L_ii| + d/2 (1 + log 2 pi)
+ * is written from L before the step (eq:argmaxELBO_advi, up to the constant
+ * the log-posterior drops). */
+vip_status vip_advi_step(vip_ctx *ctx, int32_t family, int64_t d, int32_t S, float *mu, float *L,
+                         int64_t ldl, const float *eta, const float *g, double eps,
+                         const vip_optimizer *opt_mu, const vip_optimizer *opt_L, float *grad_mu,
+                         float *grad_L, const double *logpost, double *elbo);
+
 /* Standard normals out[e], e < count, from Philox4x32-10 as described for
  * vip_ssvgd_step (device float [count]). */
 vip_status vip_philox_normals(vip_ctx *ctx, int64_t count, uint64_t seed, uint64_t stream,

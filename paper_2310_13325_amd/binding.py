@@ -36,6 +36,9 @@ VIP_FLAG_NONFINITE = 0x1
 VIP_FLAG_VMAX = 0x2
 VIP_FLAG_NOT_PD = 0x4
 VIP_FLAG_JITTER = 0x8
+VIP_ADVI_FULL_RANK = 0
+VIP_ADVI_MEAN_FIELD = 1
+VIP_ADVI_MAX_SAMPLES = 32
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
@@ -149,6 +152,10 @@ def lib() -> ctypes.CDLL:
             "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
             "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
+            "vip_advi_sample": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, i64, vp, vp]),
+            "vip_advi_step": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, i64, vp, vp, dbl,
+                                             ctypes.POINTER(VipOptimizer),
+                                             ctypes.POINTER(VipOptimizer), vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name, None)
@@ -787,3 +794,91 @@ def vip_ssvgd_step_multi(ctx: Context, xs, gs, eps, xis=None, seed=0, stream=0, 
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel())
     _check(st, "vip_(s)svgd_step_multi")
     return ws
+
+
+class Advi:
+    """Variational parameters of the ADVI Gaussian family q = N(mu, L L^T) in
+    the unconstrained space (vip_advi_sample / vip_advi_step), with the step
+    rules' state.  Full rank: L is a [d][ldl] device array (ldl = d rounded up
+    to 4) whose lower triangle L[:, :d] holds the factor; mean field: L is the
+    diagonal [d].  Starts from N(mu0, scale^2 I)."""
+
+    def __init__(self, d: int, family: int = VIP_ADVI_FULL_RANK, device=None,
+                 kind: int = VIP_OPT_ADAM, beta1: float = 0.9, beta2: float = 0.999,
+                 delta: float = 1e-8, mu0: Optional[torch.Tensor] = None, scale: float = 1.0,
+                 ldl: Optional[int] = None):
+        device = device if device is not None else torch.device("cuda", 0)
+        self.d, self.family = int(d), family
+        self.mu = (mu0.detach().to(device, torch.float32).reshape(-1).clone() if mu0 is not None
+                   else torch.zeros(d, dtype=torch.float32, device=device))
+        if family == VIP_ADVI_FULL_RANK:
+            self.ldl = int(ldl) if ldl is not None else (d + 3) // 4 * 4
+            self.L = torch.zeros(d, self.ldl, dtype=torch.float32, device=device)
+            self.L[:, :d].diagonal().fill_(scale)
+        else:
+            self.ldl = 0
+            self.L = torch.full((d,), float(scale), dtype=torch.float32, device=device)
+        self.opt_mu = Optimizer(kind, self.mu, beta1, beta2, delta)
+        self.opt_L = Optimizer(kind, self.L, beta1, beta2, delta)
+
+    def factor(self) -> torch.Tensor:
+        """L as a d x d lower-triangular (or diagonal) matrix."""
+        if self.family == VIP_ADVI_FULL_RANK:
+            return torch.tril(self.L[:, :self.d])
+        return torch.diag(self.L)
+
+    def covariance(self) -> torch.Tensor:
+        Lm = self.factor().double()
+        return Lm @ Lm.T
+
+
+def vip_advi_sample(ctx: Context, q: Advi, eta: torch.Tensor,
+                    theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """theta[s] = mu + L eta[s] (eta: [S][d] device float)."""
+    ctx.sync_stream()
+    S = eta.shape[0]
+    if theta is None:
+        theta = torch.empty(S, q.d, dtype=torch.float32, device=q.mu.device)
+    _check(lib().vip_advi_sample(ctx.handle, q.family, q.d, S, _ptr(q.mu, torch.float32),
+                                 _ptr(q.L, torch.float32), q.ldl, _ptr(eta, torch.float32),
+                                 _ptr(theta, torch.float32)), "vip_advi_sample")
+    return theta
+
+
+def vip_advi_step(ctx: Context, q: Advi, eta: torch.Tensor, g: torch.Tensor, eps: float,
+                  logpost: Optional[torch.Tensor] = None, grads: bool = False):
+    """One ascent step of q from the samples' normals eta and gradients g
+    ([S][d] each); returns (elbo or None, grad_mu or None, grad_L or None)."""
+    ctx.sync_stream()
+    S = eta.shape[0]
+    dev = q.mu.device
+    elbo = torch.empty(1, dtype=torch.float64, device=dev) if logpost is not None else None
+    gm = torch.zeros_like(q.mu) if grads else None
+    gL = torch.zeros_like(q.L) if grads else None
+    q.opt_mu.t += 1
+    q.opt_L.t += 1
+    om, ol = q.opt_mu.c(), q.opt_L.c()
+    _check(lib().vip_advi_step(ctx.handle, q.family, q.d, S, _ptr(q.mu, torch.float32),
+                               _ptr(q.L, torch.float32), q.ldl, _ptr(eta, torch.float32),
+                               _ptr(g, torch.float32), eps, ctypes.byref(om), ctypes.byref(ol),
+                               _ptr(gm, torch.float32), _ptr(gL, torch.float32),
+                               _ptr(logpost, torch.float64), _ptr(elbo, torch.float64)),
+           "vip_advi_step")
+    return elbo, gm, gL
+
+
+def vip_advi_iteration(ctx: Context, q: Advi, grid: Grid, geom: Geometry, dobs: torch.Tensor,
+                       sigma: float, prior: Prior, S: int, eps: float, seed: int, it: int,
+                       ckpt_every: int = 50, stored_steps: int = 0, live_pairs: int = 0,
+                       ws_tag: str = "advi"):
+    """One ADVI iteration on the FWI posterior: Philox normals (key seed,
+    stream it), the S samples, their log-posteriors and theta-gradients
+    (vip_grad_logpost under `prior`, normally the transform of the uniform
+    prior), and the step.  Returns the ELBO estimate (device double [1])."""
+    eta = vip_philox_normals(ctx, S * q.d, seed, it).view(S, q.d)
+    theta = vip_advi_sample(ctx, q, eta)
+    lp, g = vip_grad_logpost(ctx, grid, geom, theta.view(S, grid.nz, grid.nx), dobs, sigma,
+                             ckpt_every=ckpt_every, live_pairs=live_pairs,
+                             stored_steps=stored_steps, prior=prior, ws_tag=ws_tag)
+    elbo, _, _ = vip_advi_step(ctx, q, eta, g.view(S, q.d), eps, logpost=lp)
+    return elbo

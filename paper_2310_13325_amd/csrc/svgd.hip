@@ -30,6 +30,7 @@
 #include "vip_internal.h"
 #include "philox.h"
 #include "svgd_plan.h"
+#include "opt_rules.h"
 
 namespace vip {
 
@@ -529,40 +530,6 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
-// Step rule applied to the direction phi of one coordinate (SGD, AdaGrad,
-// AdaDelta, Adam; state s1, s2 per coordinate, FP32).
-struct OptArgs {
-  int kind;
-  float *s1, *s2;
-  float b1, b2, delta;
-  float c1, c2;   // Adam bias corrections 1 / (1 - b1^t), 1 / (1 - b2^t)
-};
-__device__ __forceinline__ float opt_step(const OptArgs &o, long long e, float p, float eps) {
-  switch (o.kind) {
-    case VIP_OPT_ADAGRAD: {
-      const float G = o.s1[e] + p * p;
-      o.s1[e] = G;
-      return eps * p / (sqrtf(G) + o.delta);
-    }
-    case VIP_OPT_ADADELTA: {
-      const float Eg = o.b1 * o.s1[e] + (1.0f - o.b1) * p * p;
-      const float Ed = o.s2[e];
-      const float u = sqrtf(Ed + o.delta) / sqrtf(Eg + o.delta) * p;
-      o.s1[e] = Eg;
-      o.s2[e] = o.b1 * Ed + (1.0f - o.b1) * u * u;
-      return eps * u;
-    }
-    case VIP_OPT_ADAM: {
-      const float mo = o.b1 * o.s1[e] + (1.0f - o.b1) * p;
-      const float ve = o.b2 * o.s2[e] + (1.0f - o.b2) * p * p;
-      o.s1[e] = mo;
-      o.s2[e] = ve;
-      return eps * (mo * o.c1) / (sqrtf(ve * o.c2) + o.delta);
-    }
-    default: return eps * p;
-  }
-}
-
 // The same update (without noise) with the product on the FP32 matrix cores
 // (v_mfma_f32_32x32x2_f32: lane l holds A[l % 32][l / 32] and B[l / 32][l % 32];
 // result register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]).
@@ -690,27 +657,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                               const vip_optimizer *opt = nullptr, int32_t kernel = VIP_KERNEL_RBF) {
   if (!ctx || !x || !g || !ws) return VIP_E_ARG;
   if (kernel != VIP_KERNEL_RBF && kernel != VIP_KERNEL_DIAG_VAR) return VIP_E_ARG;
-  OptArgs oa{VIP_OPT_SGD, nullptr, nullptr, 0.f, 0.f, 0.f, 1.f, 1.f};
-  if (opt) {
-    if (noise) return VIP_E_ARG;
-    if (opt->kind < VIP_OPT_SGD || opt->kind > VIP_OPT_ADAM) return VIP_E_ARG;
-    const bool two = opt->kind == VIP_OPT_ADADELTA || opt->kind == VIP_OPT_ADAM;
-    if (opt->kind != VIP_OPT_SGD && (!opt->s1 || (two && !opt->s2))) return VIP_E_ARG;
-    if (opt->kind == VIP_OPT_ADAM && opt->t < 1) return VIP_E_ARG;
-    if (!(opt->delta >= 0.0) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
-        !(opt->beta2 >= 0.0 && opt->beta2 < 1.0))
-      return VIP_E_ARG;
-    oa.kind = opt->kind;
-    oa.s1 = opt->s1;
-    oa.s2 = opt->s2;
-    oa.b1 = float(opt->beta1);
-    oa.b2 = float(opt->beta2);
-    oa.delta = float(opt->delta);
-    if (opt->kind == VIP_OPT_ADAM) {
-      oa.c1 = float(1.0 / (1.0 - std::pow(opt->beta1, double(opt->t))));
-      oa.c2 = float(1.0 / (1.0 - std::pow(opt->beta2, double(opt->t))));
-    }
-  }
+  OptArgs oa;
+  if (opt && noise) return VIP_E_ARG;
+  if (const vip_status st = make_opt_args(opt, &oa); st != VIP_OK) return st;
   if (n < 1 || d < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return VIP_E_ARG;
   if (bw_mode < VIP_BW_MEDIAN_ALL || bw_mode > VIP_BW_FIXED) return VIP_E_ARG;
   if (bw_mode == VIP_BW_FIXED && !(h_fixed > 0.0)) return VIP_E_ARG;
