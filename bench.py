@@ -143,19 +143,30 @@ def advi_rates(prob, S, ctx, vb, torch, sched):
     both families, and the HBM rate of the two full-rank kernels that stream
     the d(d+1)/2 entries of L (the sample reads 4 B per entry, the Adam step
     reads and writes L and two state arrays, 24 B per entry)."""
+    from paper_2310_13325_amd import autotune
     prior = vb.Prior.transform(S["lo"], S["hi"])
     d = prob.d
+    main_tile = ctx.tile_for(S["grid"])
     out = {"d": d, "prior": "uniform, transformed (eq:transform)", "rule": "adam",
            "eps": 1e-3}
     ev = lambda: torch.cuda.Event(enable_timing=True)
     for label, family, nsamp in (("full_rank_S1", vb.VIP_ADVI_FULL_RANK, 1),
                                  ("full_rank_S8", vb.VIP_ADVI_FULL_RANK, 8),
                                  ("mean_field_S1", vb.VIP_ADVI_MEAN_FIELD, 1)):
+        # the gradient call has only nsamp x 10 pairs here: tune its tile and
+        # memory schedule for that batch (untimed)
+        th = torch.zeros(nsamp, prob.nz, prob.nx, device="cuda")
+        lp = torch.empty(nsamp, dtype=torch.float64, device="cuda")
+        gg = torch.empty_like(th)
+        fn = lambda st, live: vb.vip_grad_logpost(
+            ctx, S["grid"], S["geom"], th, S["dobs"], S["sigma"], ckpt_every=prob.ckpt_every,
+            live_pairs=live, logpost=lp, grad=gg, stored_steps=st, prior=prior, ws_tag="advi")
+        tile, stored, _, _ = autotune.tune_joint(ctx, fn, [(sched["stored_steps"], 0), (0, 0)])
         q = vb.Advi(d, family, kind=vb.VIP_OPT_ADAM)
         it = lambda k: vb.vip_advi_iteration(ctx, q, S["grid"], S["geom"], S["dobs"], S["sigma"],
                                              prior, nsamp, 1e-3, seed=2310, it=k,
                                              ckpt_every=prob.ckpt_every,
-                                             stored_steps=sched["stored_steps"], ws_tag="advi")
+                                             stored_steps=stored, ws_tag="advi")
         it(0)
         torch.cuda.synchronize()
         reps = 5
@@ -166,6 +177,7 @@ def advi_rates(prob, S, ctx, vb, torch, sched):
         rate = reps / (time.perf_counter() - t)
         out[label] = {"iterations_per_s": round(rate, 3),
                       "simulations_per_s": round(rate * nsamp, 3),
+                      "tile": tile, "stored_steps": stored,
                       "elbo_last": float(elbo.item())}
         if label == "full_rank_S8":
             # the two full-rank kernels alone, HIP events on the context stream
@@ -193,6 +205,7 @@ def advi_rates(prob, S, ctx, vb, torch, sched):
         del q
         ctx._ws.pop("advi", None)
         torch.cuda.empty_cache()
+    ctx.set_tile(main_tile)
     return out
 
 

@@ -27,16 +27,18 @@ namespace vip {
 constexpr int kAdviThreads = 256;
 constexpr int kSampleRows = 8;      // rows per block of the full-rank sample
 constexpr int kSampleGroup = 8;     // samples per pass over L
-constexpr int kStepTile = 256;      // square tiles of the full-rank step
-constexpr int kStepBatch = 4;       // rows whose loads a thread issues together
+constexpr int kStepRows = 64;       // tile of the full-rank step: rows ...
+constexpr int kStepCols = 256;      // ... and columns (one per thread; 4 kStepRows)
+constexpr int kStepBatch = 8;       // rows whose loads a thread issues together
 
 // ---- full-rank sample ----------------------------------------------------------
 // A block owns kSampleRows consecutive rows and walks their columns up to the
 // last row's diagonal, one column per thread per pass, holding the SG
 // samples' eta of that column in registers, so each L entry is read once per
-// SG samples.  Block p takes row blocks p and nb-1-p, which evens out the
-// triangle.  The rows x samples partial sums are reduced across the block in
-// a fixed order.
+// SG samples.  Blocks are numbered from the bottom of the triangle up, so the
+// longest rows are dispatched first and the short ones fill in behind them.
+// The rows x samples partial sums are reduced across the block in a fixed
+// order.
 template <int SG>
 __global__ __launch_bounds__(kAdviThreads) void advi_sample_full_kernel(
     const float *__restrict__ mu, const float *__restrict__ L, long long ldl,
@@ -45,80 +47,78 @@ __global__ __launch_bounds__(kAdviThreads) void advi_sample_full_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s0 = blockIdx.y * SG;
   const long long nb = (d + kSampleRows - 1) / kSampleRows;
-  const long long p = blockIdx.x;
-  for (int half = 0; half < 2; ++half) {
-    const long long b = half == 0 ? p : nb - 1 - p;
-    if (half == 1 && b <= p) break;
-    const long long r0 = b * kSampleRows;
-    const long long rlast = (r0 + kSampleRows < d ? r0 + kSampleRows : d) - 1;
-    float acc[kSampleRows][SG];
+  const long long r0 = (nb - 1 - (long long)blockIdx.x) * kSampleRows;
+  const long long rlast = (r0 + kSampleRows < d ? r0 + kSampleRows : d) - 1;
+  float acc[kSampleRows][SG];
 #pragma unroll
-    for (int r = 0; r < kSampleRows; ++r)
+  for (int r = 0; r < kSampleRows; ++r)
 #pragma unroll
-      for (int s = 0; s < SG; ++s) acc[r][s] = 0.f;
-    for (long long c = tid; c <= rlast; c += kAdviThreads) {
-      float e[SG];
+    for (int s = 0; s < SG; ++s) acc[r][s] = 0.f;
+  for (long long c = tid; c <= rlast; c += kAdviThreads) {
+    float e[SG];
 #pragma unroll
-      for (int s = 0; s < SG; ++s) e[s] = s0 + s < S ? eta[(long long)(s0 + s) * d + c] : 0.f;
-      float v[kSampleRows];
+    for (int s = 0; s < SG; ++s) e[s] = s0 + s < S ? eta[(long long)(s0 + s) * d + c] : 0.f;
+    float v[kSampleRows];
 #pragma unroll
-      for (int r = 0; r < kSampleRows; ++r) {
-        const long long row = r0 + r;
-        v[r] = (row <= rlast && c <= row) ? L[row * ldl + c] : 0.f;
-      }
-#pragma unroll
-      for (int r = 0; r < kSampleRows; ++r)
-#pragma unroll
-        for (int s = 0; s < SG; ++s) acc[r][s] = fmaf(v[r], e[s], acc[r][s]);
-    }
-#pragma unroll
-    for (int r = 0; r < kSampleRows; ++r)
-#pragma unroll
-      for (int s = 0; s < SG; ++s) {
-        float t = acc[r][s];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (lane == 0) red[wave][r * SG + s] = t;
-      }
-    __syncthreads();
-    if (tid < kSampleRows * SG) {
-      const int r = tid / SG, s = tid % SG;
+    for (int r = 0; r < kSampleRows; ++r) {
       const long long row = r0 + r;
-      if (row <= rlast && s0 + s < S) {
-        const float t = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-        theta[(long long)(s0 + s) * d + row] = mu[row] + t;
-      }
+      v[r] = (row <= rlast && c <= row) ? L[row * ldl + c] : 0.f;
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSampleRows; ++r)
+#pragma unroll
+      for (int s = 0; s < SG; ++s) acc[r][s] = fmaf(v[r], e[s], acc[r][s]);
+  }
+#pragma unroll
+  for (int r = 0; r < kSampleRows; ++r)
+#pragma unroll
+    for (int s = 0; s < SG; ++s) {
+      float t = acc[r][s];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      if (lane == 0) red[wave][r * SG + s] = t;
+    }
+  __syncthreads();
+  if (tid < kSampleRows * SG) {
+    const int r = tid / SG, s = tid % SG;
+    const long long row = r0 + r;
+    if (row <= rlast && s0 + s < S) {
+      const float t = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      theta[(long long)(s0 + s) * d + row] = mu[row] + t;
+    }
   }
 }
 
 // ---- full-rank step --------------------------------------------------------------
-// Square kStepTile tiles of the lower triangle, tile t -> (tr, tc) with
-// tc <= tr in row-major triangular order.  A thread owns one column of the
-// tile: it keeps eta_s of that column in registers and walks the tile's rows
-// kStepBatch at a time (loads of L and state first, then the arithmetic, then
-// the stores); the tile's rows of g sit in LDS and are read as broadcasts.
-// Diagonal tiles also step mu for their rows.
+// Tiles of kStepRows rows x kStepCols columns over the lower triangle.  Row
+// block rb has floor(rb / 4) + 1 column tiles (kStepCols = 4 kStepRows), so
+// the row blocks come in quads q of 4 (q + 1) tiles and tile t decodes to
+// (rb, tc) through the quad's prefix 2 q (q + 1).  A thread owns one column
+// of its tile: it keeps eta_s of that column in registers and walks the
+// tile's rows kStepBatch at a time (loads of L and state first, then the
+// arithmetic, then the stores); the tile's rows of g sit in LDS and are read
+// as broadcasts.  The last column tile of each row block holds its diagonal
+// and also steps mu for those rows.
 template <int SG>
 __global__ __launch_bounds__(kAdviThreads) void advi_step_full_kernel(
     float *__restrict__ mu, float *__restrict__ L, long long ldl, const float *__restrict__ eta,
     const float *__restrict__ g, long long d, int S, float inv_s, float eps, OptArgs om,
     OptArgs ol, float *__restrict__ grad_mu, float *__restrict__ grad_L) {
-  __shared__ float gt[SG][kStepTile];
+  __shared__ float gt[SG][kStepRows];
   const long long t = blockIdx.x;
-  long long tr = (long long)((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
-  while (tr * (tr + 1) / 2 > t) --tr;
-  while ((tr + 1) * (tr + 2) / 2 <= t) ++tr;
-  const long long tc = t - tr * (tr + 1) / 2;
-  const long long r0 = tr * kStepTile, c0 = tc * kStepTile;
+  long long q = (long long)((sqrt(2.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (2 * q * (q + 1) > t) --q;
+  while (2 * (q + 1) * (q + 2) <= t) ++q;
+  const long long u = t - 2 * q * (q + 1);
+  const long long rb = 4 * q + u / (q + 1), tc = u % (q + 1);
+  const long long r0 = rb * kStepRows, c0 = tc * kStepCols;
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int s = 0; s < SG; ++s) {
-    const long long row = r0 + tid;
-    gt[s][tid] = (s < S && row < d) ? g[(long long)s * d + row] : 0.f;
+  for (int e = tid; e < SG * kStepRows; e += kAdviThreads) {
+    const int s = e / kStepRows, r = e % kStepRows;
+    const long long row = r0 + r;
+    gt[s][r] = (s < S && row < d) ? g[(long long)s * d + row] : 0.f;
   }
   __syncthreads();
-  if (tr == tc) {
+  if (tc == q && tid < kStepRows) {
     const long long row = r0 + tid;
     if (row < d) {
       float sum = 0.f;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kAdviThreads) void advi_step_full_kernel(
 #pragma unroll
   for (int s = 0; s < SG; ++s) e[s] = s < S ? eta[(long long)s * d + c] : 0.f;
   const long long rbeg = r0 > c ? r0 : c;
-  const long long rend = r0 + kStepTile < d ? r0 + kStepTile : d;
+  const long long rend = r0 + kStepRows < d ? r0 + kStepRows : d;
   for (long long row = rbeg; row < rend; row += kStepBatch) {
     float l[kStepBatch];
     OptState st[kStepBatch];
@@ -163,6 +163,13 @@ __global__ __launch_bounds__(kAdviThreads) void advi_step_full_kernel(
       }
     }
   }
+}
+
+// Number of tiles of advi_step_full_kernel for dimension d.
+static long long step_tiles(long long d) {
+  const long long nrb = (d + kStepRows - 1) / kStepRows;
+  const long long Q = nrb / 4;
+  return 2 * Q * (Q + 1) + (nrb - 4 * Q) * (Q + 1);
 }
 
 // ---- mean field ------------------------------------------------------------------
@@ -248,9 +255,8 @@ extern "C" vip_status vip_advi_sample(vip_ctx *ctx, int32_t family, int64_t d, i
     return VIP_OK;
   }
   const long long nb = (d + kSampleRows - 1) / kSampleRows;
-  const unsigned pairs = unsigned((nb + 1) / 2);
   const int sg = S <= kSampleGroup ? pow2_at_least(S) : kSampleGroup;
-  const dim3 grid(pairs, unsigned((S + sg - 1) / sg));
+  const dim3 grid(unsigned(nb), unsigned((S + sg - 1) / sg));
   switch (sg) {
     case 1: advi_sample_full_kernel<1><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S); break;
     case 2: advi_sample_full_kernel<2><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S); break;
@@ -289,8 +295,7 @@ extern "C" vip_status vip_advi_step(vip_ctx *ctx, int32_t family, int64_t d, int
     VIP_LAUNCH_CHECK();
     return VIP_OK;
   }
-  const long long T = (d + kStepTile - 1) / kStepTile;
-  const dim3 grid(unsigned(T * (T + 1) / 2));
+  const dim3 grid(unsigned(step_tiles(d)));
   const dim3 block(kAdviThreads);
   switch (pow2_at_least(S)) {
     case 1: advi_step_full_kernel<1><<<grid, block, 0, s>>>(mu, L, ldl, eta, g, d, S, inv_s, e, om, ol, grad_mu, grad_L); break;
