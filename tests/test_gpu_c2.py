@@ -1,0 +1,105 @@
+"""The benchmark workload at full size (c2: 200 x 120 at 20 m + 20-cell sponge,
+nt = 2000, 10 shots, 200 receivers, 128 particles) in the launch configuration
+the benchmark times (blocked tile 0, every step's a^n kept by the forward
+sweep, 640 pairs live):
+
+* three sampled particles against the FP64 C oracle: gradients <= 1e-4
+  relative L2, log-posterior <= 1e-5 relative;
+* all 128 particles against the default schedule (every segment recomputed,
+  all pairs live): the memory schedule changes only the FP32 rounding order
+  (<= 1e-5 relative L2 per particle);
+* the sSVGD step at its shape (n = 128, d = 24,000, BF16 Gram, median
+  bandwidth, clip prior) against the oracle with the same normals: D <= 1e-4,
+  K, phi and the displacement <= 1e-3, the Cholesky factor <= 1e-3.
+
+Observed data come from the C oracle (seeded noise), never from the library."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cref
+from oracle import svgd as osvgd
+from paper_2310_13325_amd import binding as vb
+from paper_2310_13325_amd import configs
+from tests.cases import build_case_c, workers
+from tests.gpu_helpers import ctx, dev, grid_geom, rel
+
+pytestmark = pytest.mark.gpu
+
+SAMPLED = (0, 77, 127)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    prob = configs.C2
+    case = build_case_c(prob)
+    assert case.particles.shape[0] == 128
+    return case
+
+
+def test_c2_gradients_in_the_benchmark_configuration(c2):
+    case = c2
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    x, dobs = dev(case.particles), dev(case.dobs)
+    lo, hi = dev(case.lo), dev(case.hi)
+    c.set_tile(0)
+    lp, g = vb.vip_grad_logpost(c, grid, geom, x, dobs, case.sigma, ckpt_every=50, lo=lo, hi=hi,
+                                stored_steps=case.prob.nt - 1, live_pairs=640, ws_tag="c2big")
+    flags = c.poll(c.workspace("c2big", 0))
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    c._ws.pop("c2big", None)
+    torch.cuda.empty_cache()
+    assert flags == 0 and np.isfinite(g).all()
+
+    lp_ref, g_ref = cref.grad_logpost(case.particles[list(SAMPLED)], case.ogrid, case.ogeom,
+                                      case.dobs, case.sigma, workers=workers())
+    for k, p in enumerate(SAMPLED):
+        e = rel(g[p], g_ref[k])
+        el = abs(lp[p] - lp_ref[k]) / abs(lp_ref[k])
+        print(f"c2 particle {p}: grad rel L2 {e:.2e}, logpost rel {el:.2e}", flush=True)
+        assert e <= 1e-4 and el <= 1e-5
+
+    # the default schedule: every segment recomputed, all pairs live
+    c.set_tile(-2)
+    lp2, g2 = vb.vip_grad_logpost(c, grid, geom, x, dobs, case.sigma, ckpt_every=50, lo=lo,
+                                  hi=hi, ws_tag="c2rec")
+    g2 = g2.cpu().numpy()
+    c._ws.pop("c2rec", None)
+    torch.cuda.empty_cache()
+    worst = max(rel(g2[p], g[p]) for p in range(g.shape[0]))
+    print(f"c2 schedules: worst per-particle grad difference {worst:.2e}", flush=True)
+    assert worst <= 1e-5
+    assert np.allclose(lp2.cpu().numpy(), lp, rtol=1e-6, atol=0)
+
+
+def test_c2_ssvgd_step_matches_oracle(c2):
+    case = c2
+    n, d = case.particles.shape[0], case.particles[0].size
+    X = case.particles.reshape(n, d)
+    r = np.random.default_rng(2310)
+    v = case.v_true.reshape(1, d)
+    G = np.float32(-(X - v) / 100.0 ** 2 + 1e-4 * r.standard_normal((n, d))).astype(np.float64)
+    xi = np.float32(r.standard_normal((n, d))).astype(np.float64)
+    eps = float(np.float32(10.0 / np.abs(G).max()))
+    lo, hi = case.lo.reshape(-1), case.hi.reshape(-1)
+    c = ctx()
+    x = dev(X)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), eps, xi=dev(xi), gram_prec=vb.VIP_GRAM_BF16,
+                           lo=dev(lo), hi=dev(hi), ws_tag="c2svgd")
+    lay = vb.svgd_layout(n, d)
+    D = vb.workspace_view(ws, lay.D, n * n, torch.float32).cpu().numpy().reshape(n, n)
+    K = vb.workspace_view(ws, lay.K, n * n, torch.float32).cpu().numpy().reshape(n, n)
+    phi = vb.workspace_view(ws, lay.phi, n * d, torch.float32).cpu().numpy().reshape(n, d)
+    L = vb.workspace_view(ws, lay.L, n * n, torch.float64).cpu().numpy().reshape(n, n)
+    flags = c.poll(ws)
+    Xr, info = osvgd.ssvgd_step(X, G, eps, xi, lo, hi)
+    errs = dict(D=rel(D, info["D"]), K=rel(K, info["K"]), phi=rel(phi, info["phi"]),
+                L=rel(L, info["L"]), dX=rel(x.cpu().numpy() - X, Xr - X))
+    print("c2 sSVGD step (BF16 Gram): " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()),
+          flush=True)
+    assert flags & ~vb.VIP_FLAG_JITTER == 0
+    assert errs["D"] <= 1e-4
+    for k in ("K", "phi", "L", "dX"):
+        assert errs[k] <= 1e-3, (k, errs[k])
+    c._ws.pop("c2svgd", None)
