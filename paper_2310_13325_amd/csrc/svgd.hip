@@ -19,9 +19,11 @@
 //               unsigned integers), then h^2 = med / (2 ln(n+1)) (1 if med = 0)
 //   rbf         K = exp(-D / (2 h^2)), row sums s (FP64 sums)
 //   cholesky    (sSVGD) L = chol(K / n) in FP64 in LDS, jitter retries
-//   update      one GEMM pass computing K (G - Xc / h^2) (on the FP32 matrix
-//               cores; with noise, and L Xi, on the vector units), then phi,
-//               the update and the clip in its epilogue.
+//   update      one GEMM pass computing K (G - Xc / h^2), then phi, the
+//               update and the clip in its epilogue: on the FP32 matrix cores
+//               for the FP32 path, on the BF16 matrix cores with both operands
+//               split into BF16 pairs for the BF16 path, on the vector units
+//               (with L Xi) for sSVGD.
 // Distances come from centred particles: D is translation invariant, and
 // centring removes the large common velocity that BF16 could not resolve.
 #include <cmath>
@@ -357,8 +359,12 @@ __global__ void bandwidth_kernel(const uint32_t *sel, long long count, int n, in
 }
 
 // ---- kernel matrix and row sums ---------------------------------------------
+// With khi non-null the row is also written as BF16 pairs k = hi + lo
+// (hi = bf16(k), lo = bf16(k - hi)) in rows of ldk, zero past column n.
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 __global__ __launch_bounds__(256) void rbf_kernel(const float *D, const double *h2, float *K,
-                                                  float *s, int n) {
+                                                  float *s, int n, uint16_t *khi, uint16_t *klo,
+                                                  int ldk) {
   __shared__ double part[4];
   const int i = blockIdx.x;
   const float inv = float(1.0 / (2.0 * h2[0]));
@@ -367,7 +373,17 @@ __global__ __launch_bounds__(256) void rbf_kernel(const float *D, const double *
     float k = expf(-D[(long long)i * n + j] * inv);
     K[(long long)i * n + j] = k;
     acc += double(k);
+    if (khi) {
+      const uint16_t h = f32_to_bf16_rne(k);
+      khi[(long long)i * ldk + j] = h;
+      klo[(long long)i * ldk + j] = f32_to_bf16_rne(k - bf16_to_f32(h));
+    }
   }
+  if (khi)
+    for (int j = n + int(threadIdx.x); j < ldk; j += 256) {
+      khi[(long long)i * ldk + j] = 0;
+      klo[(long long)i * ldk + j] = 0;
+    }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -647,6 +663,170 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
+// The same update with the product K B on the BF16 matrix cores, each FP32
+// operand split into a BF16 pair x = hi + lo (hi = bf16(x), lo = bf16(x - hi))
+// and the product taken as hi hi + hi lo + lo hi.  The dropped lo lo term and
+// the rounding of lo stay below 2^-16 of each product, under the error the
+// BF16 Gram already puts into K; this is the update of the BF16 path.
+//
+// bpair_kernel forms B = G Q^-1 - Xc / h^2 once and splits it, rows j and
+// j + 1 interleaved as 32-bit pairs (the k order of a matrix-core operand),
+// rows padded with zeros to ldk and columns to dp.
+__global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float *xc,
+                                                    const float *vq, const double *h2,
+                                                    uint32_t *bph, uint32_t *bpl, int n,
+                                                    long long d, long long dp, int npairs) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)npairs * dp) return;
+  const long long a = e % dp;
+  const int p = int(e / dp);
+  const float inv_h2 = float(1.0 / h2[0]);
+  uint16_t h[2] = {0, 0}, l[2] = {0, 0};
+  for (int q = 0; q < 2; ++q) {
+    const int j = 2 * p + q;
+    if (j < n && a < d) {
+      float gv = g[(long long)j * d + a];
+      if (vq) gv *= vq[a];
+      const float b = fmaf(-xc[(long long)j * d + a], inv_h2, gv);
+      h[q] = f32_to_bf16_rne(b);
+      l[q] = f32_to_bf16_rne(b - bf16_to_f32(h[q]));
+    }
+  }
+  bph[e] = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
+  bpl[e] = uint32_t(l[0]) | (uint32_t(l[1]) << 16);
+}
+
+// Block: 256 particles x 256 coordinates, 8 waves (4 x 2) of 2 x 4 tiles of
+// 32 x 32 (v_mfma_f32_32x32x16_bf16, operand and result layout as in the Gram
+// kernel); the particle index j runs in stages of 32 through LDS, the next
+// stage prefetched into registers.  A = K rows i (K is symmetric) with 32
+// consecutive j from the split copy; a B fragment is four 32-bit pairs of
+// its column.  The three products go over all eight tiles in turn, so that
+// consecutive matrix instructions accumulate into different tiles.
+constexpr int VM = 256, VN = 256, VK = 32, VKP = VK + 8, VBP = VN + 4, VT = 512;
+__global__ __launch_bounds__(VT) void update_bf16x3_kernel(
+    const uint16_t *khi, const uint16_t *klo, int ldk, const uint32_t *bph, const uint32_t *bpl,
+    long long dp, const float *xc, const float *s, const double *h2, float *x, float *phi,
+    const float *lo, const float *hi, int n, long long d, int mblocks, float eps, OptArgs opt,
+    uint32_t *status) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[VM][VKP];   // Ah[i][k] = hi(K[i0 + i][j0 + k])
+  __shared__ __attribute__((aligned(16))) uint16_t Al[VM][VKP];
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[VK / 2][VBP];   // Bh[p][a] = pair j0 + 2p, + 1
+  __shared__ __attribute__((aligned(16))) uint32_t Bl[VK / 2][VBP];
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  const int nt = mblocks * int((d + VN - 1) / VN);
+  if (tb >= nt) return;
+  const int i0 = (tb % mblocks) * VM;
+  const long long a0 = (long long)(tb / mblocks) * VN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+
+  // staging: A row t / 2, k half 16 (t % 2); B pair row t / 32, columns
+  // 8 (t % 32) .. + 7
+  const int ar = t >> 1, ak = (t & 1) * 16;
+  const int bp = t >> 5, bc = (t & 31) * 8;
+  const bool bin = a0 + bc < dp;   // dp is a multiple of 8: the 8 columns are all in or all out
+  uint4 pah[2], pal[2], pbh[2], pbl[2];
+  auto load_stage = [&](int j0) {
+    const int i = i0 + ar;
+    if (i < n) {
+      const uint16_t *ph = khi + (long long)i * ldk + j0 + ak;
+      const uint16_t *pl = klo + (long long)i * ldk + j0 + ak;
+      pah[0] = *reinterpret_cast<const uint4 *>(ph);
+      pah[1] = *reinterpret_cast<const uint4 *>(ph + 8);
+      pal[0] = *reinterpret_cast<const uint4 *>(pl);
+      pal[1] = *reinterpret_cast<const uint4 *>(pl + 8);
+    } else {
+      pah[0] = pah[1] = pal[0] = pal[1] = make_uint4(0, 0, 0, 0);
+    }
+    if (bin) {
+      const long long off = (long long)(j0 / 2 + bp) * dp + a0 + bc;
+      pbh[0] = *reinterpret_cast<const uint4 *>(bph + off);
+      pbh[1] = *reinterpret_cast<const uint4 *>(bph + off + 4);
+      pbl[0] = *reinterpret_cast<const uint4 *>(bpl + off);
+      pbl[1] = *reinterpret_cast<const uint4 *>(bpl + off + 4);
+    } else {
+      pbh[0] = pbh[1] = pbl[0] = pbl[1] = make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto store_stage = [&]() {
+    *reinterpret_cast<uint4 *>(&Ah[ar][ak]) = pah[0];
+    *reinterpret_cast<uint4 *>(&Ah[ar][ak + 8]) = pah[1];
+    *reinterpret_cast<uint4 *>(&Al[ar][ak]) = pal[0];
+    *reinterpret_cast<uint4 *>(&Al[ar][ak + 8]) = pal[1];
+    *reinterpret_cast<uint4 *>(&Bh[bp][bc]) = pbh[0];
+    *reinterpret_cast<uint4 *>(&Bh[bp][bc + 4]) = pbh[1];
+    *reinterpret_cast<uint4 *>(&Bl[bp][bc]) = pbl[0];
+    *reinterpret_cast<uint4 *>(&Bl[bp][bc + 4]) = pbl[1];
+  };
+
+  f32x16_t acc[2][4];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  load_stage(0);
+  for (int j0 = 0; j0 < n; j0 += VK) {
+    __syncthreads();               // the previous stage's tiles are no longer read
+    store_stage();
+    __syncthreads();
+    if (j0 + VK < n) load_stage(j0 + VK);
+#pragma unroll
+    for (int kk = 0; kk < VK; kk += 16) {
+      const int kq = kk + 8 * (lane >> 5);   // first of my 8 k
+      bf16x8_t fah[2], fal[2], fbh[4], fbl[4];
+      for (int m = 0; m < 2; ++m) {
+        const int row = wi * 64 + m * 32 + (lane & 31);
+        const uint4 rh = *reinterpret_cast<const uint4 *>(&Ah[row][kq]);
+        const uint4 rl = *reinterpret_cast<const uint4 *>(&Al[row][kq]);
+        __builtin_memcpy(&fah[m], &rh, 16);
+        __builtin_memcpy(&fal[m], &rl, 16);
+      }
+      for (int q = 0; q < 4; ++q) {
+        const int col = wj * 128 + q * 32 + (lane & 31);
+        uint32_t uh[4], ul[4];
+        for (int e = 0; e < 4; ++e) {
+          uh[e] = Bh[kq / 2 + e][col];
+          ul[e] = Bl[kq / 2 + e][col];
+        }
+        __builtin_memcpy(&fbh[q], uh, 16);
+        __builtin_memcpy(&fbl[q], ul, 16);
+      }
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[m], fbh[q], acc[m][q], 0, 0, 0);
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbl[q], acc[m][q], 0, 0, 0);
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbh[q], acc[m][q], 0, 0, 0);
+    }
+  }
+
+  const float inv_n = 1.0f / float(n);
+  const float inv_h2 = float(1.0 / h2[0]);
+  bool bad = false;
+  for (int m = 0; m < 2; ++m)
+    for (int r = 0; r < 16; ++r) {
+      const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (i >= n) continue;
+      const float si = s[i] * inv_h2;
+      for (int q = 0; q < 4; ++q) {
+        const long long a = a0 + wj * 128 + q * 32 + (lane & 31);
+        if (a >= d) continue;
+        const long long e = (long long)i * d + a;
+        const float p = fmaf(si, xc[e], acc[m][q][r]) * inv_n;
+        phi[e] = p;
+        float v = x[e] + opt_step(opt, e, p, eps);
+        if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
+        bad |= !isfinite(v);
+        x[e] = v;
+      }
+    }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+}
+
 // ---- host ---------------------------------------------------------------------
 
 static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
@@ -726,7 +906,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   }
   bandwidth_kernel<<<dim3(1), dim3(1), 0, s>>>(P.sel, count, n, bw_mode, h_fixed, P.h2, h2_out);
   VIP_LAUNCH_CHECK();
-  rbf_kernel<<<dim3(n), dim3(256), 0, s>>>(P.D, P.h2, P.K, P.s, n);
+  const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
+  rbf_kernel<<<dim3(n), dim3(256), 0, s>>>(P.D, P.h2, P.K, P.s, n,
+                                           split_update ? P.khi : nullptr, P.klo, P.ldk);
   VIP_LAUNCH_CHECK();
 
   dim3 ugrid(unsigned((d + 63) / 64), unsigned((n + 63) / 64));
@@ -753,9 +935,21 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     const int vec = (d % 4 == 0) && (n % 4 == 0) && (reinterpret_cast<uintptr_t>(g) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
-    update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
-        P.K, g, P.xc, vq, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa,
-        P.status);
+    if (split_update) {
+      const int npairs = P.ldk / 2;
+      const long long nb = ((long long)npairs * P.dp + 255) / 256;
+      bpair_kernel<<<dim3(unsigned(nb)), dim3(256), 0, s>>>(g, P.xc, vq, P.h2, P.bph, P.bpl, n, d,
+                                                           P.dp, npairs);
+      VIP_LAUNCH_CHECK();
+      const int vblocks = (n + VM - 1) / VM;
+      const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
+      update_bf16x3_kernel<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
+          P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d,
+          vblocks, float(eps), oa, P.status);
+    } else
+      update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
+          P.K, g, P.xc, vq, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa,
+          P.status);
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;

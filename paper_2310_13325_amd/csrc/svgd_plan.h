@@ -17,6 +17,10 @@ struct SvgdPlan {
   uint32_t *hist = nullptr, *sel = nullptr;
   double *h2 = nullptr, *L = nullptr;
   float *Lf = nullptr, *xi = nullptr, *phi = nullptr;
+  uint16_t *khi = nullptr, *klo = nullptr;   // K split into BF16 pairs, rows of ldk
+  uint32_t *bph = nullptr, *bpl = nullptr;   // B split, rows (j, j + 1) interleaved, pitch dp
+  int ldk = 0;
+  long long dp = 0;
   int nbt = 0, splits = 0;
   long long kspan = 0;
   size_t bytes = 0;
@@ -54,6 +58,12 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->Lf = A.take<float>(nn);
   P->xi = A.take<float>(nd);
   P->phi = A.take<float>(nd);
+  P->ldk = (n + 31) / 32 * 32;
+  P->khi = A.take<uint16_t>(size_t(n) * size_t(P->ldk));
+  P->klo = A.take<uint16_t>(size_t(n) * size_t(P->ldk));
+  P->dp = (d + 7) / 8 * 8;
+  P->bph = A.take<uint32_t>(size_t(P->ldk / 2) * size_t(P->dp));
+  P->bpl = A.take<uint32_t>(size_t(P->ldk / 2) * size_t(P->dp));
   P->bytes = A.bytes();
 }
 
