@@ -105,7 +105,7 @@ __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
   for (int i = ty; i < n; i += CENTRE_GROUPS) {
     const long long e = (long long)i * d + a;
     const float v = x[e] - m;
-    xc[e] = v;
+    if (xc) xc[e] = v;
     xc16[e] = f32_to_bf16_rne(sq ? v * sc : v);
   }
 }
@@ -325,20 +325,38 @@ __global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, 
   }
 }
 
-__global__ void radix_select_kernel(uint32_t *sel, uint32_t *hist, int shift) {
-  if (threadIdx.x >= 2) return;
-  const int t = threadIdx.x;
+// One wave per target: each lane holds 4 bins, a wave prefix sum finds the
+// lane whose bins contain the rank, that lane resolves the bin; the
+// histogram is then cleared for the next pass.
+__global__ __launch_bounds__(128) void radix_select_kernel(uint32_t *sel, uint32_t *hist,
+                                                           int shift) {
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint32_t *s = sel + 3 * t;
-  uint32_t k = s[2];
   uint32_t *h = hist + 256 * t;
-  uint32_t b = 0;
-  for (; b < 255; ++b) {
-    if (k < h[b]) break;
-    k -= h[b];
+  const uint32_t k = s[2];
+  const uint32_t b0 = h[4 * lane], b1 = h[4 * lane + 1], b2 = h[4 * lane + 2], b3 = h[4 * lane + 3];
+  uint32_t incl = b0 + b1 + b2 + b3;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
   }
-  s[0] |= b << shift;
-  s[1] |= 0xFFu << shift;
-  s[2] = k;
+  const unsigned long long hit = __ballot(incl > k);
+  const int first = hit ? __ffsll(hit) - 1 : 63;
+  if (lane == first) {
+    const uint32_t excl = incl - (b0 + b1 + b2 + b3);
+    uint32_t r = k - excl, b = 4 * lane;
+    const uint32_t bins[4] = {b0, b1, b2, b3};
+    int e = 0;
+    for (; e < 3; ++e) {
+      if (r < bins[e]) break;
+      r -= bins[e];
+    }
+    b += e;
+    s[0] |= b << shift;
+    s[1] |= 0xFFu << shift;
+    s[2] = r;
+  }
+  h[4 * lane] = h[4 * lane + 1] = h[4 * lane + 2] = h[4 * lane + 3] = 0;
 }
 
 __global__ void bandwidth_kernel(const uint32_t *sel, long long count, int n, int mode,
@@ -669,11 +687,13 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
 // the rounding of lo stay below 2^-16 of each product, under the error the
 // BF16 Gram already puts into K; this is the update of the BF16 path.
 //
-// bpair_kernel forms B = G Q^-1 - Xc / h^2 once and splits it, rows j and
+// bpair_kernel forms B = G Q^-1 - Xc / h^2 once (Xc = x - xbar recomputed, the
+// centring kernel does not store it on this path) and splits it, rows j and
 // j + 1 interleaved as 32-bit pairs (the k order of a matrix-core operand),
 // rows padded with zeros to ldk and columns to dp.
-__global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float *xc,
-                                                    const float *vq, const double *h2,
+__global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float *x,
+                                                    const float *xbar, const float *vq,
+                                                    const double *h2,
                                                     uint32_t *bph, uint32_t *bpl, int n,
                                                     long long d, long long dp, int npairs) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -687,7 +707,8 @@ __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float 
     if (j < n && a < d) {
       float gv = g[(long long)j * d + a];
       if (vq) gv *= vq[a];
-      const float b = fmaf(-xc[(long long)j * d + a], inv_h2, gv);
+      const float xcv = x[(long long)j * d + a] - xbar[a];   // the centring kernel's Xc
+      const float b = fmaf(-xcv, inv_h2, gv);
       h[q] = f32_to_bf16_rne(b);
       l[q] = f32_to_bf16_rne(b - bf16_to_f32(h[q]));
     }
@@ -706,7 +727,7 @@ __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float 
 constexpr int VM = 256, VN = 256, VK = 32, VKP = VK + 8, VBP = VN + 4, VT = 512;
 __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     const uint16_t *khi, const uint16_t *klo, int ldk, const uint32_t *bph, const uint32_t *bpl,
-    long long dp, const float *xc, const float *s, const double *h2, float *x, float *phi,
+    long long dp, const float *xbar, const float *s, const double *h2, float *x, float *phi,
     const float *lo, const float *hi, int n, long long d, int mblocks, float eps, OptArgs opt,
     uint32_t *status) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[VM][VKP];   // Ah[i][k] = hi(K[i0 + i][j0 + k])
@@ -816,9 +837,10 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
         const long long a = a0 + wj * 128 + q * 32 + (lane & 31);
         if (a >= d) continue;
         const long long e = (long long)i * d + a;
-        const float p = fmaf(si, xc[e], acc[m][q][r]) * inv_n;
+        const float xe = x[e];
+        const float p = fmaf(si, xe - xbar[a], acc[m][q][r]) * inv_n;
         phi[e] = p;
-        float v = x[e] + opt_step(opt, e, p, eps);
+        float v = xe + opt_step(opt, e, p, eps);
         if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
         bad |= !isfinite(v);
         x[e] = v;
@@ -869,9 +891,11 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
 
   const bool diag = kernel == VIP_KERNEL_DIAG_VAR;
   float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
+  // the BF16 path without noise never reads the FP32 Xc (it recomputes x - xbar)
+  const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
   centre_kernel<<<dim3(unsigned((d + CENTRE_COLS - 1) / CENTRE_COLS)),
-                  dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(x, P.xbar, P.xc, P.xc16, sq, vq, n,
-                                                             d, P.status);
+                  dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(
+      x, P.xbar, split_update ? nullptr : P.xc, P.xc16, sq, vq, n, d, P.status);
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;
   dim3 ggrid(unsigned(nup * P.splits));
@@ -894,19 +918,18 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     VIP_TRY(upload_i32(s, reinterpret_cast<int32_t *>(P.sel), sel_init, 6));
     if (count > 0) {
       unsigned hb = unsigned(std::min<long long>((nn + 255) / 256, 1024));
+      VIP_TRY(fill_u32(s, P.hist, 512, 0u));   // each select clears it for the next pass
       for (int shift = 24; shift >= 0; shift -= 8) {
-        VIP_TRY(fill_u32(s, P.hist, 512, 0u));
         radix_hist_kernel<<<dim3(hb), dim3(256), 0, s>>>(P.D, n, bw_mode == VIP_BW_MEDIAN_OFFDIAG,
                                                          shift, P.sel, P.hist);
         VIP_LAUNCH_CHECK();
-        radix_select_kernel<<<dim3(1), dim3(64), 0, s>>>(P.sel, P.hist, shift);
+        radix_select_kernel<<<dim3(1), dim3(128), 0, s>>>(P.sel, P.hist, shift);
         VIP_LAUNCH_CHECK();
       }
     }
   }
   bandwidth_kernel<<<dim3(1), dim3(1), 0, s>>>(P.sel, count, n, bw_mode, h_fixed, P.h2, h2_out);
   VIP_LAUNCH_CHECK();
-  const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
   rbf_kernel<<<dim3(n), dim3(256), 0, s>>>(P.D, P.h2, P.K, P.s, n,
                                            split_update ? P.khi : nullptr, P.klo, P.ldk);
   VIP_LAUNCH_CHECK();
@@ -938,13 +961,13 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     if (split_update) {
       const int npairs = P.ldk / 2;
       const long long nb = ((long long)npairs * P.dp + 255) / 256;
-      bpair_kernel<<<dim3(unsigned(nb)), dim3(256), 0, s>>>(g, P.xc, vq, P.h2, P.bph, P.bpl, n, d,
-                                                           P.dp, npairs);
+      bpair_kernel<<<dim3(unsigned(nb)), dim3(256), 0, s>>>(g, x, P.xbar, vq, P.h2, P.bph, P.bpl,
+                                                           n, d, P.dp, npairs);
       VIP_LAUNCH_CHECK();
       const int vblocks = (n + VM - 1) / VM;
       const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
       update_bf16x3_kernel<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
-          P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xc, P.s, P.h2, x, P.phi, lo, hi, n, d,
+          P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, lo, hi, n, d,
           vblocks, float(eps), oa, P.status);
     } else
       update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
