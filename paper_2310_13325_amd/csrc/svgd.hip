@@ -136,9 +136,14 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, fl
   __shared__ __attribute__((aligned(16))) uint16_t As[GB][GKP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[GB][GKP];
   const int nup = nbt * (nbt + 1) / 2;
-  const int split = blockIdx.x / nup;
+  // tile index, contiguous per XCD (blocks are dealt round-robin over 8 XCDs),
+  // so that blocks of one k range that share rows meet in one L2
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  if (tb >= nup * int((d + kspan - 1) / kspan)) return;
+  const int split = tb / nup;
   int bi, bj;
-  upper_block(blockIdx.x - split * nup, nbt, bi, bj);
+  upper_block(tb - split * nup, nbt, bi, bj);
   const int i0 = bi * GB, j0 = bj * GB;
   const long long k0 = (long long)split * kspan;
   const long long k1 = min(d, k0 + kspan);
@@ -210,9 +215,14 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, const fl
   __shared__ __attribute__((aligned(16))) float As[GF_K][GB + GF_P];
   __shared__ __attribute__((aligned(16))) float Bs[GF_K][GB + GF_P];
   const int nup = nbt * (nbt + 1) / 2;
-  const int split = blockIdx.x / nup;
+  // tile index, contiguous per XCD (blocks are dealt round-robin over 8 XCDs),
+  // so that blocks of one k range that share rows meet in one L2
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  if (tb >= nup * int((d + kspan - 1) / kspan)) return;
+  const int split = tb / nup;
   int bi, bj;
-  upper_block(blockIdx.x - split * nup, nbt, bi, bj);
+  upper_block(tb - split * nup, nbt, bi, bj);
   const int i0 = bi * GB, j0 = bj * GB;
   const long long k0 = (long long)split * kspan;
   const long long k1 = min(d, k0 + kspan);
@@ -898,7 +908,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       x, P.xbar, split_update ? nullptr : P.xc, P.xc16, sq, vq, n, d, P.status);
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;
-  dim3 ggrid(unsigned(nup * P.splits));
+  dim3 ggrid(unsigned((nup * P.splits + 7) / 8 * 8));
   if (gram_prec == VIP_GRAM_BF16)
     gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan, P.nbt);
   else
