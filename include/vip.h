@@ -311,7 +311,7 @@ vip_status vip_adjoint_tape(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
 #define VIP_BW_MEDIAN_OFFDIAG 1  /* median of the n(n-1)/2 distinct pairs */
 #define VIP_BW_FIXED 2           /* h = h_fixed */
 #define VIP_GRAM_BF16 0          /* X_c X_c^T on BF16 matrix cores, FP32 accumulation */
-#define VIP_GRAM_FP32 1          /* X_c X_c^T in FP32 on the vector units */
+#define VIP_GRAM_FP32 1          /* X_c X_c^T in FP32 on the FP32 matrix cores */
 
 /* Workspace bytes for vip_svgd_step / vip_ssvgd_step with n particles of
  * dimension d. */
@@ -334,7 +334,12 @@ vip_status vip_svgd_layout_of(int32_t n, int64_t d, vip_svgd_layout *out);
  *   phi_i = 1/n [ sum_j K_ij g_j + (s_i x_i - sum_j K_ij x_j) / h^2 ];
  *   x_i <- clip(x_i + eps phi_i) (clip only with a uniform prior).
  * Distances come from the Gram matrix of the centred particles, on BF16 matrix
- * cores or in FP32 (gram_prec).  h2_out: device double [1] or NULL. */
+ * cores or in FP32 (gram_prec).  The product K (G - X_c / h^2) behind phi runs
+ * in FP32 on the FP32 matrix cores with VIP_GRAM_FP32; with VIP_GRAM_BF16 it
+ * runs on the BF16 matrix cores with each FP32 operand split into a BF16 pair
+ * (hi + lo, products hi hi + hi lo + lo hi, FP32 accumulation: within 2^-16 of
+ * each product, below the error of the BF16 Gram).  h2_out: device double [1]
+ * or NULL. */
 vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
                          int32_t bw_mode, double h_fixed, int32_t gram_prec,
                          const vip_prior *prior, double *h2_out, void *ws, size_t ws_bytes);
