@@ -85,16 +85,27 @@ struct BlockArgs {
   int acc_flush;          // ADJ: last launch of the segment (adds into acc64, acc32 not written)
 };
 
-// LDS of one block, per mode: double-buffered u; the adjoint also keeps c.
+constexpr int kLdsBytes = 160 * 1024;
+// The adjoint keeps c of each point in LDS when that still lets two blocks
+// share a CU (registers are then tight), and in registers otherwise (one
+// block per CU leaves registers to spare, and the LDS reads go).
+template <int EX, int EZ>
+constexpr bool adj_c_in_lds() {
+  constexpr int U = (EZ + 4) * (EX + 4) * 4, C = EZ * EX * 4, T = 8 * EZ + 64;
+  return 2 * (U + C + T) <= kLdsBytes;
+}
+
+// LDS of one block, per mode: double-buffered u; the adjoint may also keep c.
 template <int MODE, int EX, int EZ, int TMAX>
 struct BlockLds {
   static constexpr bool ADJ = MODE == BMODE_ADJ;
+  static constexpr bool CLDS = ADJ && adj_c_in_lds<EX, EZ>();
   static constexpr int LW = EX + 4;           // 2 zero cells each side
   float u[2][EZ + 4][LW];
   float gz[EZ];                               // z damping per tile row (0 off the grid)
   int rr[EZ];                                 // receiver-row index per tile row (-1: none)
   float inj[TMAX];                            // forward / recompute: w(t_n)/(dx dz) per step
-  float c[ADJ ? EZ : 1][ADJ ? EX : 1];        // adjoint: c per point
+  float c[CLDS ? EZ : 1][CLDS ? EX : 1];      // adjoint: c per point
 };
 
 template <int EX, int EZ, int TMAX>
@@ -113,20 +124,22 @@ __device__ __forceinline__ int xcd_tile() {
 }
 
 // LDS bytes of one single-problem block with nbuf u buffers.
-constexpr int kLdsBytes = 160 * 1024;
 template <int MODE, int EX, int EZ>
 constexpr int block_lds_bytes(int nbuf) {
-  return nbuf * (EZ + 4) * (EX + 4) * 4 + (MODE == BMODE_ADJ ? EZ * EX * 4 : 0) + 8 * EZ + 64;
+  return nbuf * (EZ + 4) * (EX + 4) * 4 +
+         (MODE == BMODE_ADJ && adj_c_in_lds<EX, EZ>() ? EZ * EX * 4 : 0) + 8 * EZ + 64;
 }
 // u buffers: two when two blocks fit in one CU's LDS that way; else one if
 // that lets two blocks share a CU (one block's loads and stores then overlap
 // the other's steps, at the price of a second barrier per step); else two.
-// The modes that store a^n keep two: with one they need more registers than
-// two blocks leave.
+// The modes that store a^n, and the adjoint with c in registers, keep two:
+// with one they need more registers than two blocks leave.
 template <int MODE, int EX, int EZ>
 constexpr int block_nbuf() {
   return 2 * block_lds_bytes<MODE, EX, EZ>(2) <= kLdsBytes ? 2
-         : MODE != BMODE_REC && MODE != BMODE_FWS && 2 * block_lds_bytes<MODE, EX, EZ>(1) <= kLdsBytes
+         : MODE != BMODE_REC && MODE != BMODE_FWS &&
+                   !(MODE == BMODE_ADJ && !adj_c_in_lds<EX, EZ>()) &&
+                   2 * block_lds_bytes<MODE, EX, EZ>(1) <= kLdsBytes
              ? 1
              : 2;
 }
@@ -147,12 +160,13 @@ __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<MODE, EX, EZ, RZ>()))) voi
   constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
   constexpr bool ADJ = MODE == BMODE_ADJ;
   constexpr int NBUF = block_nbuf<MODE, EX, EZ>();
+  constexpr bool CLDS = ADJ && adj_c_in_lds<EX, EZ>();
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
   __shared__ float lds[NBUF][EZ + 4][LW];
   __shared__ float gzs[EZ];     // z damping of each extended-tile row (0 outside the grid)
   __shared__ int rrs[EZ];       // receiver-row index of each extended-tile row (-1: none)
   __shared__ float injs[TMAX];  // forward / recompute: source term w(t_n)/(dx dz) of each step
-  __shared__ float cs[ADJ ? EZ : 1][ADJ ? EX : 1];     // adjoint: c of each point
+  __shared__ float cs[CLDS ? EZ : 1][CLDS ? EX : 1];   // adjoint: c of each point (or registers)
   const int t = xcd_tile();
   if (t >= a.total_tiles) return;
 #include "fd_block_body.inc"
@@ -167,6 +181,7 @@ __device__ __forceinline__ void fd_block_multi_body(const BlockArgs &a, const in
   constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
   constexpr bool ADJ = MODE == BMODE_ADJ;
   constexpr int NBUF = 2;
+  constexpr bool CLDS = BlockLds<MODE, EX, EZ, TMAX>::CLDS;
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
   auto &lds = sh.u;
   auto &gzs = sh.gz;
