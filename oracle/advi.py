@@ -102,3 +102,30 @@ def run(grad_logpost, mu, L, etas, eps, kind=optim.ADAM, family=FULL_RANK, **rul
         elbos.append(elbo(lp, L, family))
         mu, L, _, _ = step(mu, L, eta, g, eps, kind, state_mu, state_L, family, **rule)
     return mu, L, np.array(elbos)
+
+
+def sample_rows(mu, L_rows, eta, rows):
+    """theta[s][i] for the listed coordinates only, from those rows of the
+    full-rank factor (L_rows[k] = row rows[k] of L, entries past the diagonal
+    ignored): the reparameterisation of eq:normal one coordinate at a time."""
+    eta = np.atleast_2d(np.asarray(eta, dtype=np.float64))
+    out = np.empty((eta.shape[0], len(rows)))
+    for k, i in enumerate(rows):
+        Li = np.asarray(L_rows[k][: i + 1], dtype=np.float64)
+        out[:, k] = float(mu[i]) + eta[:, : i + 1] @ Li
+    return out
+
+
+def gradient_rows(L_rows, eta, g, rows):
+    """Rows of grad_L (eq:gradient_L) for the listed coordinates: entry (i, j),
+    j <= i, is 1/S sum_s g_s[i] eta_s[j], plus 1 / L_ii on the diagonal (the
+    lower part of (L^-1)^T)."""
+    eta = np.atleast_2d(np.asarray(eta, dtype=np.float64))
+    g = np.atleast_2d(np.asarray(g, dtype=np.float64))
+    S = eta.shape[0]
+    out = []
+    for k, i in enumerate(rows):
+        row = g[:, i] @ eta[:, : i + 1] / S
+        row[i] += 1.0 / float(L_rows[k][i])
+        out.append(row)
+    return out

@@ -271,3 +271,49 @@ def test_iteration_helper_equals_the_call_sequence():
     elbo_b, _, _ = vb.vip_advi_step(c, qb, eta, g.view(3, d), 1e-3, logpost=lp)
     assert torch.equal(qa.mu, qb.mu) and torch.equal(qa.L, qb.L) and torch.equal(elbo, elbo_b)
     assert math.isfinite(elbo.item())
+
+
+def test_full_rank_at_the_benchmark_size_on_sampled_rows():
+    """d = 24,000 (the c2 model), S = 8 and the Adam rule, as the benchmark
+    times the full-rank kernels: sampled rows of theta, of grad_L and of the
+    updated L against the oracle computed one row at a time."""
+    d, S = 24000, 8
+    r = np.random.default_rng(2024)
+    L = r.standard_normal((d, d), dtype=np.float32)
+    L *= np.float32(0.01)
+    L = np.tril(L)
+    L[np.diag_indices(d)] = r.uniform(0.5, 2.0, d).astype(np.float32)
+    mu = _f32(r.normal(0.0, 1.0, d))
+    eta = _f32(r.standard_normal((S, d)))
+    g = _f32(r.normal(0.0, 5.0, (S, d)))
+    rows = [0, 1, 255, 256, 4097, 12345, 23998, 23999]
+    L_rows = [L[i].astype(np.float64) for i in rows]
+    c = ctx()
+    q = _q_from(L, mu, vb.VIP_ADVI_FULL_RANK, vb.VIP_OPT_ADAM, d)
+    del L
+    th = vb.vip_advi_sample(c, q, dev(eta)).cpu().numpy().astype(np.float64)
+    ref = oadvi.sample_rows(mu, L_rows, eta, rows)
+    scale = np.stack([np.abs(mu[i]) + np.abs(eta[:, : i + 1]) @ np.abs(L_rows[k][: i + 1])
+                      for k, i in enumerate(rows)], axis=1)
+    e_th = (np.abs(th[:, rows] - ref) / scale).max()
+    _, _, gL = vb.vip_advi_step(c, q, dev(eta), dev(g), 1e-3, grads=True)
+    g_ref = oadvi.gradient_rows(L_rows, eta, g, rows)
+    idx = torch.tensor(rows, device="cuda")
+    gL_rows = gL.index_select(0, idx).cpu().numpy().astype(np.float64)
+    L_new = q.L.index_select(0, idx).cpu().numpy().astype(np.float64)
+    e_g = e_L = 0.0
+    for k, i in enumerate(rows):
+        gs = np.abs(g[:, i]) @ np.abs(eta[:, : i + 1]) / S
+        gs[i] += 1.0 / abs(L_rows[k][i])
+        e_g = max(e_g, (np.abs(gL_rows[k][: i + 1] - g_ref[k]) / gs).max())
+        inc = ooptim.step(ooptim.ADAM, g_ref[k], {}, 1e-3, beta1=0.9, beta2=0.999, delta=1e-8)
+        # Adam's first step is eps g / (|g| + delta): where |g| is within FP32
+        # rounding of 0 its sign is not determined, so those entries are left out
+        keep = np.abs(g_ref[k]) > 1e-5 * gs
+        e_L = max(e_L, np.abs(L_new[k][: i + 1] - (L_rows[k][: i + 1] + inc))[keep].max())
+        assert (L_new[k][i + 1:] == 0).all()
+    print(f"d={d} S={S} sampled rows: theta {e_th:.2e}, grad_L {e_g:.2e}, L' max abs {e_L:.2e}",
+          flush=True)
+    assert e_th <= 1e-5 and e_g <= 1e-5 and e_L <= 1e-6
+    del q, gL
+    torch.cuda.empty_cache()

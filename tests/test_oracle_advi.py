@@ -182,3 +182,18 @@ def test_inverse_term_keeps_its_structural_zeros_for_ill_conditioned_factors():
     zero = np.zeros((1, d))
     _, gL = advi.gradients(L, zero, zero)
     assert np.array_equal(gL, np.diag(1.0 / np.diag(L)))
+
+
+def test_row_functions_agree_with_the_full_matrix_functions():
+    r = np.random.default_rng(19)
+    d, S = 40, 3
+    mu = r.standard_normal(d)
+    L = np.tril(r.normal(0, 0.3, (d, d))) + np.diag(r.uniform(0.5, 2.0, d))
+    eta, g = r.standard_normal((S, d)), r.standard_normal((S, d))
+    rows = [0, 7, 39]
+    th = advi.sample(mu, L, eta)
+    assert np.allclose(advi.sample_rows(mu, L[rows], eta, rows), th[:, rows], rtol=1e-13, atol=1e-13)
+    _, gL = advi.gradients(L, eta, g)
+    for k, i in enumerate(rows):
+        assert np.allclose(advi.gradient_rows(L[rows], eta, g, rows)[k], gL[i, : i + 1],
+                           rtol=1e-12, atol=1e-12)
