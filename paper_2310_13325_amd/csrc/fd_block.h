@@ -161,6 +161,8 @@ __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<MODE, EX, EZ, RZ>()))) voi
   constexpr bool ADJ = MODE == BMODE_ADJ;
   constexpr int NBUF = block_nbuf<MODE, EX, EZ>();
   constexpr bool CLDS = ADJ && adj_c_in_lds<EX, EZ>();
+  // one block per CU leaves registers for g of each row
+  constexpr bool GREG = block_waves_per_eu<MODE, EX, EZ, RZ>() == 1;
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
   __shared__ float lds[NBUF][EZ + 4][LW];
   __shared__ float gzs[EZ];     // z damping of each extended-tile row (0 outside the grid)
@@ -182,6 +184,7 @@ __device__ __forceinline__ void fd_block_multi_body(const BlockArgs &a, const in
   constexpr bool ADJ = MODE == BMODE_ADJ;
   constexpr int NBUF = 2;
   constexpr bool CLDS = BlockLds<MODE, EX, EZ, TMAX>::CLDS;
+  constexpr bool GREG = false;
   static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
   auto &lds = sh.u;
   auto &gzs = sh.gz;
