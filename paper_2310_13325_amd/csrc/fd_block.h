@@ -63,6 +63,7 @@ struct BlockArgs {
   int n_start;            // FWD/REC: first input time index; ADJ: first n (produces z^{n+1}), descending
   int seg_n0;             // REC/FWS/ADJ: time index of segment slot 0
   float w1x, w2x, w1z, w2z;   // Laplacian weights 4/3, -1/12 times 1/dx^2 (x) or 1/dz^2 (z)
+  int iso;                    // w1x == w1z and w2x == w2z (dx == dz): the fused Laplacian applies
   float inv_area;
   const float *gx, *gz, *c;
   const int *src_idx, *rrow, *rmap;
@@ -151,7 +152,7 @@ constexpr int block_waves_per_eu() {
              : 1;
 }
 
-template <int MODE, int EX, int EZ, int RZ, int TMAX>
+template <int MODE, int EX, int EZ, int RZ, int TMAX, bool ISO>
 __global__ __launch_bounds__(EX *(EZ / RZ))
 __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<MODE, EX, EZ, RZ>()))) void fd_block(BlockArgs a) {
   constexpr int NTHREADS = EX * (EZ / RZ);
@@ -174,7 +175,7 @@ __attribute__((amdgpu_waves_per_eu(block_waves_per_eu<MODE, EX, EZ, RZ>()))) voi
 #include "fd_block_body.inc"
 }
 
-template <int MODE, int EX, int EZ, int RZ, int TMAX>
+template <int MODE, int EX, int EZ, int RZ, int TMAX, bool ISO>
 __device__ __forceinline__ void fd_block_multi_body(const BlockArgs &a, const int t,
                                                     BlockLds<MODE, EX, EZ, TMAX> &sh) {
   constexpr int NTHREADS = EX * (EZ / RZ);
@@ -213,10 +214,22 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_block_multi(MultiArgs m) {
   int p = 0;
   while (p + 1 < m.nprob && t >= m.start[p + 1]) ++p;
   const int local = t - m.start[p];
+  // the same Laplacian form as the single-problem kernel, so a problem's
+  // result does not depend on the company it is launched in
+  const bool iso = m.a[p].iso;
   switch (m.mode[p]) {
-    case BMODE_FWD: fd_block_multi_body<BMODE_FWD, EX, EZ, RZ, TMAX>(m.a[p], local, sh.fwd); break;
-    case BMODE_REC: fd_block_multi_body<BMODE_REC, EX, EZ, RZ, TMAX>(m.a[p], local, sh.rec); break;
-    default: fd_block_multi_body<BMODE_ADJ, EX, EZ, RZ, TMAX>(m.a[p], local, sh.adj); break;
+    case BMODE_FWD:
+      if (iso) fd_block_multi_body<BMODE_FWD, EX, EZ, RZ, TMAX, true>(m.a[p], local, sh.fwd);
+      else fd_block_multi_body<BMODE_FWD, EX, EZ, RZ, TMAX, false>(m.a[p], local, sh.fwd);
+      break;
+    case BMODE_REC:
+      if (iso) fd_block_multi_body<BMODE_REC, EX, EZ, RZ, TMAX, true>(m.a[p], local, sh.rec);
+      else fd_block_multi_body<BMODE_REC, EX, EZ, RZ, TMAX, false>(m.a[p], local, sh.rec);
+      break;
+    default:
+      if (iso) fd_block_multi_body<BMODE_ADJ, EX, EZ, RZ, TMAX, true>(m.a[p], local, sh.adj);
+      else fd_block_multi_body<BMODE_ADJ, EX, EZ, RZ, TMAX, false>(m.a[p], local, sh.adj);
+      break;
   }
 }
 

@@ -485,14 +485,20 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
   const long long total = a.total_tiles;
   const dim3 grid(unsigned((total + 7) / 8 * 8)), block(unsigned(tc.ex * (tc.ez / tc.rz)));
   hipStream_t s = ctx->s();
-#define VIP_BLOCK_CASE(C, EX, EZ, RZ, TM)                                              \
-  if (cfg == C) {                                                                      \
-    if (mode == BMODE_FWD) fd_block<BMODE_FWD, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
-    else if (mode == BMODE_REC) fd_block<BMODE_REC, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
-    else if (mode == BMODE_FWS) fd_block<BMODE_FWS, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a); \
-    else fd_block<BMODE_ADJ, EX, EZ, RZ, TM><<<grid, block, 0, s>>>(a);               \
-    VIP_LAUNCH_CHECK();                                                                \
-    return VIP_OK;                                                                     \
+#define VIP_BLOCK_MODES(EX, EZ, RZ, TM, ISO)                                                   \
+  if (mode == BMODE_FWD) fd_block<BMODE_FWD, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);        \
+  else if (mode == BMODE_REC) fd_block<BMODE_REC, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);   \
+  else if (mode == BMODE_FWS) fd_block<BMODE_FWS, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);   \
+  else fd_block<BMODE_ADJ, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);
+#define VIP_BLOCK_CASE(C, EX, EZ, RZ, TM)      \
+  if (cfg == C) {                              \
+    if (a.iso) {                               \
+      VIP_BLOCK_MODES(EX, EZ, RZ, TM, true)    \
+    } else {                                   \
+      VIP_BLOCK_MODES(EX, EZ, RZ, TM, false)   \
+    }                                          \
+    VIP_LAUNCH_CHECK();                        \
+    return VIP_OK;                             \
   }
   VIP_BLOCK_CASE(0, 112, 112, 14, 8)
   VIP_BLOCK_CASE(1, 80, 80, 10, 4)
@@ -500,6 +506,7 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
   VIP_BLOCK_CASE(3, 64, 64, 8, 4)
   VIP_BLOCK_CASE(4, 128, 64, 8, 4)
 #undef VIP_BLOCK_CASE
+#undef VIP_BLOCK_MODES
   return VIP_E_UNSUPPORTED;
 }
 
@@ -569,6 +576,7 @@ static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wav
   a.w2x = float(-1.0 / 12.0 * D.inv_dx2);
   a.w1z = float(4.0 / 3.0 * D.inv_dz2);
   a.w2z = float(-1.0 / 12.0 * D.inv_dz2);
+  a.iso = a.w1x == a.w1z && a.w2x == a.w2z;
   a.inv_area = D.inv_area;
   a.gx = P.gx;
   a.gz = P.gz;
