@@ -4,8 +4,9 @@ mean-field family of section 5) through the C ABI against the FP64 oracle.
 Bars: samples and gradients elementwise within 1e-5 of the scale of the
 terms they sum (FP32 sums of up to d products); updated parameters within
 1e-6 relative L2 after three steps of every step rule; the ELBO estimate
-within 1e-12 relative (FP64 on both sides, from the same FP32 L); entries of
-L above the diagonal and the padding past column d never written (a NaN sentinel stays bitwise
+within 1e-12 relative plus 1e-6 per diagonal entry (FP64 sums; the device's L
+carries FP32 rounding of earlier steps); entries of L above the diagonal and
+the padding past column d never written (a NaN sentinel stays bitwise
 intact and never reaches a result); the FWI loop (transform prior) within
 1e-3 of the oracle's displacement of mu and L after three iterations."""
 import math
@@ -95,8 +96,7 @@ def test_full_rank_step_matches_oracle(kind, d, ldl, S):
         eta = _f32(r.standard_normal((S, d)))
         g = _f32(r.normal(0.0, 5.0, (S, d)))
         lp = r.normal(-1e4, 10.0, S)
-        # the ELBO is taken from the device's own L before the step
-        ref_elbo = oadvi.elbo(lp, np.tril(q.L.cpu().numpy()[:, :d].astype(np.float64)))
+        ref_elbo = oadvi.elbo(lp, L_r)   # the oracle's own L before the step
         elbo, gm, gL = vb.vip_advi_step(c, q, dev(eta), dev(g), eps,
                                         logpost=dev(lp, torch.float64), grads=True)
         mu_r, L_r, gm_r, gL_r = oadvi.step(mu_r, L_r, eta, g, eps, kind, st_mu, st_L,
@@ -110,12 +110,14 @@ def test_full_rank_step_matches_oracle(kind, d, ldl, S):
         Lg = q.L.cpu().numpy()
         e_mu = rel(q.mu.cpu().numpy(), mu_r)
         e_L = rel(Lg[:, :d][low], L_r[low])
-        e_elbo = abs(elbo.item() - ref_elbo) / abs(ref_elbo)
+        # FP64 sums on both sides; the device's L_ii carry FP32 rounding of the
+        # earlier steps, at most ~1e-6 relative each, so |d log L_ii| <= 1e-6
+        e_elbo = abs(elbo.item() - ref_elbo) / (1e-12 * abs(ref_elbo) + 1e-6 * d)
         print(f"rule {kind} d={d} S={S} step {step}: grad_mu {e_gm:.1e} grad_L {e_gL:.1e} "
               f"mu {e_mu:.1e} L {e_L:.1e} elbo {e_elbo:.1e}", flush=True)
         assert e_gm <= 1e-5 and e_gL <= 1e-5
         assert e_mu <= 1e-6 and e_L <= 1e-6
-        assert e_elbo <= 1e-12
+        assert e_elbo <= 1.0
         # untouched: NaN sentinel above the diagonal and in the padding columns,
         # state arrays there still zero
         up = np.triu_indices(d, 1)
@@ -138,7 +140,7 @@ def test_mean_field_step_matches_oracle(kind):
         eta = _f32(r.standard_normal((S, d)))
         g = _f32(r.normal(0.0, 5.0, (S, d)))
         lp = r.normal(-1e4, 10.0, S)
-        ref_elbo = oadvi.elbo(lp, q.L.cpu().numpy().astype(np.float64), oadvi.MEAN_FIELD)
+        ref_elbo = oadvi.elbo(lp, l_r, oadvi.MEAN_FIELD)
         elbo, gm, gl = vb.vip_advi_step(c, q, dev(eta), dev(g), 1e-3,
                                         logpost=dev(lp, torch.float64), grads=True)
         mu_r, l_r, gm_r, gl_r = oadvi.step(mu_r, l_r, eta, g, 1e-3, kind, st_mu, st_l,
@@ -147,7 +149,7 @@ def test_mean_field_step_matches_oracle(kind):
         assert (np.abs(gl.cpu().numpy() - gl_r) / scale).max() <= 1e-5
         assert np.abs(gm.cpu().numpy() - gm_r).max() <= 1e-5 * np.abs(g).mean(axis=0).max()
         assert rel(q.mu.cpu().numpy(), mu_r) <= 1e-6 and rel(q.L.cpu().numpy(), l_r) <= 1e-6
-        assert abs(elbo.item() - ref_elbo) <= 1e-12 * abs(ref_elbo)
+        assert abs(elbo.item() - ref_elbo) <= 1e-12 * abs(ref_elbo) + 1e-6 * d
 
 
 def test_step_rejects_bad_arguments():

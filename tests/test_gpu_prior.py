@@ -62,8 +62,10 @@ def test_transform_prior_plain_path_and_round_trip():
     n = theta.shape[0]
     m_ref = oprior.to_model(theta.reshape(n, -1), lo, hi)
     assert rel(m.reshape(n, -1), m_ref) <= 1e-7
-    back = vb.vip_prior_transform(c, pr, dev(m), to_theta=True).cpu().numpy()
-    th_ref = oprior.to_theta(np.float32(m).astype(np.float64).reshape(n, -1), lo, hi)
+    # the inverse map on the oracle's models (rounded to FP32)
+    m32 = np.float32(m_ref).astype(np.float64)
+    back = vb.vip_prior_transform(c, pr, dev(m32.reshape(m.shape)), to_theta=True).cpu().numpy()
+    th_ref = oprior.to_theta(m32, lo, hi)
     assert np.abs(back.reshape(n, -1) - th_ref).max() <= 1e-5 * max(1.0, np.abs(th_ref).max())
 
 
