@@ -127,10 +127,29 @@ def cpu_baseline(prob, S, ctx, vb, torch, workers):
     g = g.cpu().numpy().astype(np.float64)
     err_g = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     err_lp = float(abs(lp.cpu().numpy()[0] - lp_ref[0]) / abs(lp_ref[0]))
+    # one core: shot 0 of the same particle in this process, scaled to all shots
+    geom1 = ofwi.Geometry(src_iz=(prob.src_iz,), src_ix=(prob.src_ix[0],),
+                          rec_iz=(prob.rec_iz,) * prob.nr, rec_ix=prob.rec_ix, f0=prob.f0)
+    t1 = time.perf_counter()
+    ofwi.data_gradient(part[0], grid, geom1, dobs[:1], sigma)
+    one_shot = time.perf_counter() - t1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     base = {"value": round(1.0 / wall, 5), "unit": "particle-gradients/s", "cores": workers,
             "kind": "oracle",
             "sample": f"1 particle x {prob.ns} shots of the workload, FP64 NumPy, one process "
-                      f"per shot on {workers} host cores, {wall:.1f} s wall"}
+                      f"per shot on {workers} host cores, {wall:.1f} s wall",
+            "value_1core": round(1.0 / (one_shot * prob.ns), 5),
+            "sample_1core": f"shot 0 of the same particle in one process ({one_shot:.1f} s), "
+                            f"times {prob.ns} shots",
+            "cpu_model": model}
     err = {"grad_rel_l2": err_g, "logpost_rel": err_lp, "against": "FP64 oracle, 1 particle"}
     return base, err
 
@@ -339,9 +358,14 @@ def main():
     ach = kinds[dom]["alg_GBps"]
     traffic = traffic_from_counters({"tile": tile, "stored_steps": sched["stored_steps"],
                                      "live_pairs": sched["live_pairs"]})
+    tr = None if traffic is None else traffic.get(dom)
+    meas = None if tr is None else round(tr / (kinds[dom]["avg_launch_us"] * 1e-6) / 1e9, 1)
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else traffic.get(dom),
+                "traffic": tr,
+                # counter-measured HBM bytes per launch over the live launch time
+                "measured_GBps": meas,
+                "measured_frac": None if meas is None else round(meas / HBM_PEAK_GBS, 4),
                 "kernel": f"{kname}, {dom} mode", "modes": kinds,
                 "alu": {"achieved": kinds[dom]["alg_TFLOPs"], "peak": ALU_PEAK_TFLOPS,
                         "unit": "TFLOP/s",
