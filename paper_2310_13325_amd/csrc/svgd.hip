@@ -128,7 +128,7 @@ __device__ __forceinline__ void upper_block(int u, int nb, int &bi, int &bj) {
 // of each operand; result register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4,
 // column l % 32.
 constexpr int GB = 128;   // block edge
-constexpr int GK = 64;    // k per LDS stage
+constexpr int GK = 32;    // k per LDS stage
 constexpr int GKP = GK + 8;
 
 __global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, float *part, int n,
@@ -155,9 +155,9 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, fl
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
   const bool vec_ok = (d % 8) == 0;
   for (long long kb = k0; kb < k1; kb += GK) {
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < GB * GK / 8 / 256; ++it) {
       int idx = t + it * 256;
-      int row = idx >> 3, ch = idx & 7;
+      int row = idx / (GK / 8), ch = idx % (GK / 8);
       long long kc = kb + ch * 8;
       uint4 va = make_uint4(0, 0, 0, 0), vbv = make_uint4(0, 0, 0, 0);
       if (vec_ok && kc + 8 <= k1) {
