@@ -93,6 +93,21 @@ def test_svgd_bf16_gram_matches_oracle(n, d):
     assert g["h2"] == pytest.approx(_median_rule(g["D"], n, vb.VIP_BW_MEDIAN_ALL), rel=1e-15)
 
 
+@pytest.mark.parametrize("n,d", [(1, 5), (2, 37), (33, 257), (257, 33)])
+def test_bf16_path_small_and_ragged_shapes(n, d):
+    """The BF16 path (BF16 Gram, split-BF16 update: K rows padded to 32, B
+    pairs padded in both directions) on shapes that are not multiples of its
+    tiles.  With few coordinates the BF16 Gram is coarse (2^-9 per product,
+    little averaging over d), so the bound is phi within 5e-3; indexing and
+    padding mistakes show as O(1) errors or non-finite values."""
+    g, r, c, ws = _run(n, d, seed=7 * n + d, gram=vb.VIP_GRAM_BF16)
+    e_phi = rel(g["phi"], r["phi"])
+    print(f"bf16 path n={n} d={d}: phi rel L2 {e_phi:.2e}", flush=True)
+    assert np.isfinite(g["phi"]).all() and np.isfinite(g["X"]).all()
+    assert e_phi <= 5e-3
+    assert c.poll(ws) == 0
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 6])
 def test_median_modes_small_n(n):
     k12 = {vb.VIP_BW_MEDIAN_ALL: 1.0 / 9.0, vb.VIP_BW_MEDIAN_OFFDIAG: 1.0 / 3.0}
