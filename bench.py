@@ -435,9 +435,12 @@ def main():
         log(f"plain path: {1.0 / tp:.3f} particle-gradients/s")
     if not args.no_c5:
         case = configs.C5
-        gen = torch.Generator(device="cuda").manual_seed(case.seed)
-        Xc = 3000.0 + case.spread * torch.randn(case.n, case.d, device="cuda", generator=gen)
-        Gc = -(Xc - 3000.0) / case.spread ** 2
+        # the c5 inputs: the c2 model perturbed by smoothed seeded fields, and
+        # gradients pulling towards it (the parity test's generator)
+        Xn, Gn = synth.svgd_precision_case(case, S["v_true"])
+        Xc = torch.as_tensor(Xn, dtype=torch.float32, device="cuda")
+        Gc = torch.as_tensor(Gn, dtype=torch.float32, device="cuda")
+        del Xn, Gn
         svgd = {}
         for name, prec in (("bf16_gram", vb.VIP_GRAM_BF16), ("fp32_gram", vb.VIP_GRAM_FP32)):
             Xw = Xc.clone()
@@ -460,6 +463,16 @@ def main():
             diag()
         torch.cuda.synchronize()
         svgd["bf16_gram_diag_kernel"] = round(reps / (time.perf_counter() - t), 2)
+        # matrix-core work of one BF16-path step: the Gram's 136 upper 128 x 128
+        # blocks of 256 (2 n^2 d x 136/256) and the split update's three
+        # products (3 x 2 n^2 d), against the dense BF16 peak
+        nn_d = 2.0 * case.n * case.n * case.d
+        nb = (case.n + 127) // 128
+        work = nn_d * (nb * (nb + 1) / 2) / nb ** 2 + 3.0 * nn_d
+        svgd["bf16_path_matrix_core"] = {
+            "flops_per_step": work, "achieved_TFLOPs": round(work * svgd["bf16_gram"] / 1e12, 1),
+            "peak_TFLOPs": 2500.0, "frac": round(work * svgd["bf16_gram"] / 2.5e15, 4),
+            "profile": "profiles/svgd_c5.md (per-kernel MFMA busy from counters)"}
         extra["svgd_steps_per_s"] = {"n": case.n, "d": case.d, **svgd}
         log(f"svgd c5: {svgd}")
         ctx._ws.pop("c5", None)
