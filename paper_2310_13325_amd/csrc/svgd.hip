@@ -554,17 +554,34 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
   }
   const float inv_n = 1.0f / float(n);
   bool bad = false;
+  // All loads first, then the arithmetic and stores (the stores could alias
+  // the loads as far as the compiler knows, which would serialise them).
+  float xv[4][4], cv[4][4];
+#pragma unroll
   for (int r = 0; r < 4; ++r) {
-    int i = i0 + ty * 4 + r;
+    const int i = i0 + ty * 4 + r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const long long a = a0 + tx * 4 + c;
+      const bool in = i < n && a < d;
+      const long long e = (long long)i * d + a;
+      xv[r][c] = in ? x[e] : 0.0f;
+      cv[r][c] = in ? xc[e] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + ty * 4 + r;
     if (i >= n) break;
     const float si = s[i] * inv_h2;
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      long long a = a0 + tx * 4 + c;
+      const long long a = a0 + tx * 4 + c;
       if (a >= d) break;
-      long long e = (long long)i * d + a;
-      float p = fmaf(si, xc[e], kb[r][c]) * inv_n;
+      const long long e = (long long)i * d + a;
+      const float p = fmaf(si, cv[r][c], kb[r][c]) * inv_n;
       phi[e] = p;
-      float v = x[e] + eps * p;
+      float v = xv[r][c] + eps * p;
       if (NOISE) v += (vq ? noise_scale * sqrtf(vq[a]) : noise_scale) * lz[r][c];
       if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
       bad |= !isfinite(v);
@@ -585,6 +602,7 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
 // Blocks that share a column range are consecutive per XCD, so its B tiles
 // meet in one L2.
 constexpr int UM = 256, UN = 128, UK = 16, UP = 4, UT = 512;
+template <bool RULE>
 __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const float *g,
                                                          const float *xc, const float *vq,
                                                          const float *s,
@@ -671,23 +689,76 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
 
   const float inv_n = 1.0f / float(n);
   bool bad = false;
-  for (int m = 0; m < 2; ++m)
-    for (int r = 0; r < 16; ++r) {
-      const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (i >= n) continue;
-      const float si = s[i] * inv_h2;
-      for (int q = 0; q < 2; ++q) {
-        const long long a = a0 + wj * 64 + q * 32 + (lane & 31);
-        if (a >= d) continue;
-        const long long e = (long long)i * d + a;
-        const float p = fmaf(si, xc[e], acc[m][q][r]) * inv_n;
-        phi[e] = p;
-        float v = x[e] + opt_step(opt, e, p, eps);
-        if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
-        bad |= !isfinite(v);
-        x[e] = v;
+  if constexpr (RULE) {
+    // a step rule with per-coordinate state: one element at a time
+    for (int m = 0; m < 2; ++m)
+      for (int r = 0; r < 16; ++r) {
+        const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i >= n) continue;
+        const float si = s[i] * inv_h2;
+        for (int q = 0; q < 2; ++q) {
+          const long long a = a0 + wj * 64 + q * 32 + (lane & 31);
+          if (a >= d) continue;
+          const long long e = (long long)i * d + a;
+          const float p = fmaf(si, xc[e], acc[m][q][r]) * inv_n;
+          phi[e] = p;
+          float v = x[e] + opt_step(opt, e, p, eps);
+          if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
+          bad |= !isfinite(v);
+          x[e] = v;
+        }
       }
+  } else {
+    // Plain steps, four result registers (eight elements) at a time: the
+    // batch's loads of xc and x are all issued before its stores (which could
+    // alias them as far as the compiler knows).  Register r of sub-tile m is
+    // row 8 (r / 4) + r % 4 + m 32 past my first.
+    const int lrow = wi * 64 + 4 * (lane >> 5);
+    const int lcol = wj * 64 + (lane & 31);
+    const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
+    float lov[2], hiv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const long long a = a0 + lcol + q * 32;
+      lov[q] = (lo && a < d) ? lo[a] : 0.0f;
+      hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
     }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int rb = 0; rb < 16; rb += 4) {
+        float xv[4][2], cv[4][2], si[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
+          const int i = i0 + lrow + lr;
+          si[rr] = i < n ? s[i] * inv_h2 : 0.0f;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const bool in = i < n && a0 + lcol + q * 32 < d;
+            const long long e = el + (long long)lr * d + q * 32;
+            xv[rr][q] = in ? x[e] : 0.0f;
+            cv[rr][q] = in ? xc[e] : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
+          if (i0 + lrow + lr >= n) continue;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            if (a0 + lcol + q * 32 >= d) continue;
+            const long long e = el + (long long)lr * d + q * 32;
+            const float p = fmaf(si[rr], cv[rr][q], acc[m][q][r]) * inv_n;
+            phi[e] = p;
+            float v = xv[rr][q] + eps * p;
+            if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
+            bad |= !isfinite(v);
+            x[e] = v;
+          }
+        }
+      }
+  }
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
@@ -735,6 +806,7 @@ __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float 
 // its column.  The three products go over all eight tiles in turn, so that
 // consecutive matrix instructions accumulate into different tiles.
 constexpr int VM = 256, VN = 256, VK = 32, VKP = VK + 8, VBP = VN + 4, VT = 512;
+template <bool RULE>
 __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     const uint16_t *khi, const uint16_t *klo, int ldk, const uint32_t *bph, const uint32_t *bpl,
     long long dp, const float *xbar, const float *s, const double *h2, float *x, float *phi,
@@ -838,24 +910,77 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
   const float inv_n = 1.0f / float(n);
   const float inv_h2 = float(1.0 / h2[0]);
   bool bad = false;
-  for (int m = 0; m < 2; ++m)
-    for (int r = 0; r < 16; ++r) {
-      const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (i >= n) continue;
-      const float si = s[i] * inv_h2;
-      for (int q = 0; q < 4; ++q) {
-        const long long a = a0 + wj * 128 + q * 32 + (lane & 31);
-        if (a >= d) continue;
-        const long long e = (long long)i * d + a;
-        const float xe = x[e];
-        const float p = fmaf(si, xe - xbar[a], acc[m][q][r]) * inv_n;
-        phi[e] = p;
-        float v = xe + opt_step(opt, e, p, eps);
-        if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
-        bad |= !isfinite(v);
-        x[e] = v;
+  if constexpr (RULE) {
+    // a step rule with per-coordinate state: one element at a time
+    for (int m = 0; m < 2; ++m)
+      for (int r = 0; r < 16; ++r) {
+        const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i >= n) continue;
+        const float si = s[i] * inv_h2;
+        for (int q = 0; q < 4; ++q) {
+          const long long a = a0 + wj * 128 + q * 32 + (lane & 31);
+          if (a >= d) continue;
+          const long long e = (long long)i * d + a;
+          const float xe = x[e];
+          const float p = fmaf(si, xe - xbar[a], acc[m][q][r]) * inv_n;
+          phi[e] = p;
+          float v = xe + opt_step(opt, e, p, eps);
+          if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
+          bad |= !isfinite(v);
+          x[e] = v;
+        }
       }
+  } else {
+    // Plain steps, four rows at a time: every x of the batch is loaded before
+    // any store, so the loads are in flight together (the stores to phi and x
+    // could alias them as far as the compiler knows, which would otherwise
+    // serialise each load behind the previous element's stores).  Element
+    // (r, q) of sub-tile m sits at el + (m 32 + 8 (r / 4) + r % 4) d + 32 q.
+    const int lrow = wi * 64 + 4 * (lane >> 5);      // my first local row
+    const int lcol = wj * 128 + (lane & 31);         // my first local column
+    const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
+    float xb[4], lov[4], hiv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long a = a0 + lcol + q * 32;
+      xb[q] = a < d ? xbar[a] : 0.0f;
+      lov[q] = (lo && a < d) ? lo[a] : 0.0f;
+      hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
     }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int rb = 0; rb < 16; rb += 4) {
+        const int lr = m * 32 + 8 * (rb >> 2);   // row of r = rb, relative to my first
+        float xv[4][4], si[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int i = i0 + lrow + lr + rr;
+          si[rr] = i < n ? s[i] * inv_h2 : 0.0f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool in = i < n && a0 + lcol + q * 32 < d;
+            xv[rr][q] = in ? x[el + (long long)(lr + rr) * d + q * 32] : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (i0 + lrow + lr + rr >= n) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (a0 + lcol + q * 32 >= d) continue;
+            const long long e = el + (long long)(lr + rr) * d + q * 32;
+            const float xe = xv[rr][q];
+            const float p = fmaf(si[rr], xe - xb[q], acc[m][q][rb + rr]) * inv_n;
+            phi[e] = p;
+            float v = xe + eps * p;
+            if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
+            bad |= !isfinite(v);
+            x[e] = v;
+          }
+        }
+      }
+  }
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
@@ -976,13 +1101,16 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       VIP_LAUNCH_CHECK();
       const int vblocks = (n + VM - 1) / VM;
       const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
-      update_bf16x3_kernel<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
+      auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x3_kernel<false> : update_bf16x3_kernel<true>;
+      kern<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
           P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, lo, hi, n, d,
           vblocks, float(eps), oa, P.status);
-    } else
-      update_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
+    } else {
+      auto *kern = oa.kind == VIP_OPT_SGD ? update_mfma_kernel<false> : update_mfma_kernel<true>;
+      kern<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
           P.K, g, P.xc, vq, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa,
           P.status);
+    }
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;
