@@ -803,9 +803,12 @@ __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float 
 // kernel); the particle index j runs in stages of 32 through LDS, the next
 // stage prefetched into registers.  A = K rows i (K is symmetric) with 32
 // consecutive j from the split copy; a B fragment is four 32-bit pairs of
-// its column.  The three products go over all eight tiles in turn, so that
-// consecutive matrix instructions accumulate into different tiles.
-constexpr int VM = 256, VN = 256, VK = 32, VKP = VK + 8, VBP = VN + 4, VT = 512;
+// its column, kept column by column in LDS (16 pairs and 4 cells of padding
+// per column, so that the 16-byte fragment reads of 16 lanes meet distinct
+// banks) and read with one 16-byte load.  The three products go over all
+// eight tiles in turn, so that consecutive matrix instructions accumulate
+// into different tiles.
+constexpr int VM = 256, VN = 256, VK = 32, VKP = VK + 8, VBT = VK / 2 + 4, VT = 512;
 template <bool RULE>
 __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     const uint16_t *khi, const uint16_t *klo, int ldk, const uint32_t *bph, const uint32_t *bpl,
@@ -814,8 +817,8 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     uint32_t *status) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[VM][VKP];   // Ah[i][k] = hi(K[i0 + i][j0 + k])
   __shared__ __attribute__((aligned(16))) uint16_t Al[VM][VKP];
-  __shared__ __attribute__((aligned(16))) uint32_t Bh[VK / 2][VBP];   // Bh[p][a] = pair j0 + 2p, + 1
-  __shared__ __attribute__((aligned(16))) uint32_t Bl[VK / 2][VBP];
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[VN][VBT];   // Bh[a][p] = pair j0 + 2p, + 1
+  __shared__ __attribute__((aligned(16))) uint32_t Bl[VN][VBT];
   const int per = int(gridDim.x) >> 3;
   const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
   const int nt = mblocks * int((d + VN - 1) / VN);
@@ -825,11 +828,11 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
 
-  // staging: A row t / 2, k half 16 (t % 2); B pair row t / 32, columns
-  // 8 (t % 32) .. + 7
+  // staging: A row t / 2, k half 16 (t % 2); B pair row lane % 16 and
+  // columns bcol + 16 h .. + 3 (h = 0, 1), bcol = 32 w + 4 (lane / 16): the
+  // transposed LDS stores of one instruction then meet 64 distinct banks
   const int ar = t >> 1, ak = (t & 1) * 16;
-  const int bp = t >> 5, bc = (t & 31) * 8;
-  const bool bin = a0 + bc < dp;   // dp is a multiple of 8: the 8 columns are all in or all out
+  const int bp = lane & 15, bcol = w * 32 + 4 * (lane >> 4);
   uint4 pah[2], pal[2], pbh[2], pbl[2];
   auto load_stage = [&](int j0) {
     const int i = i0 + ar;
@@ -843,14 +846,13 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     } else {
       pah[0] = pah[1] = pal[0] = pal[1] = make_uint4(0, 0, 0, 0);
     }
-    if (bin) {
-      const long long off = (long long)(j0 / 2 + bp) * dp + a0 + bc;
-      pbh[0] = *reinterpret_cast<const uint4 *>(bph + off);
-      pbh[1] = *reinterpret_cast<const uint4 *>(bph + off + 4);
-      pbl[0] = *reinterpret_cast<const uint4 *>(bpl + off);
-      pbl[1] = *reinterpret_cast<const uint4 *>(bpl + off + 4);
-    } else {
-      pbh[0] = pbh[1] = pbl[0] = pbl[1] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // dp is a multiple of 8: the 4 columns are all in or all out
+      const long long a = a0 + bcol + 16 * h;
+      const long long off = (long long)(j0 / 2 + bp) * dp + a;
+      pbh[h] = a < dp ? *reinterpret_cast<const uint4 *>(bph + off) : make_uint4(0, 0, 0, 0);
+      pbl[h] = a < dp ? *reinterpret_cast<const uint4 *>(bpl + off) : make_uint4(0, 0, 0, 0);
     }
   };
   auto store_stage = [&]() {
@@ -858,10 +860,18 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     *reinterpret_cast<uint4 *>(&Ah[ar][ak + 8]) = pah[1];
     *reinterpret_cast<uint4 *>(&Al[ar][ak]) = pal[0];
     *reinterpret_cast<uint4 *>(&Al[ar][ak + 8]) = pal[1];
-    *reinterpret_cast<uint4 *>(&Bh[bp][bc]) = pbh[0];
-    *reinterpret_cast<uint4 *>(&Bh[bp][bc + 4]) = pbh[1];
-    *reinterpret_cast<uint4 *>(&Bl[bp][bc]) = pbl[0];
-    *reinterpret_cast<uint4 *>(&Bl[bp][bc + 4]) = pbl[1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = bcol + 16 * h;
+      Bh[c][bp] = pbh[h].x;
+      Bh[c + 1][bp] = pbh[h].y;
+      Bh[c + 2][bp] = pbh[h].z;
+      Bh[c + 3][bp] = pbh[h].w;
+      Bl[c][bp] = pbl[h].x;
+      Bl[c + 1][bp] = pbl[h].y;
+      Bl[c + 2][bp] = pbl[h].z;
+      Bl[c + 3][bp] = pbl[h].w;
+    }
   };
 
   f32x16_t acc[2][4];
@@ -887,13 +897,10 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
       }
       for (int q = 0; q < 4; ++q) {
         const int col = wj * 128 + q * 32 + (lane & 31);
-        uint32_t uh[4], ul[4];
-        for (int e = 0; e < 4; ++e) {
-          uh[e] = Bh[kq / 2 + e][col];
-          ul[e] = Bl[kq / 2 + e][col];
-        }
-        __builtin_memcpy(&fbh[q], uh, 16);
-        __builtin_memcpy(&fbl[q], ul, 16);
+        const uint4 uh = *reinterpret_cast<const uint4 *>(&Bh[col][kq / 2]);
+        const uint4 ul = *reinterpret_cast<const uint4 *>(&Bl[col][kq / 2]);
+        __builtin_memcpy(&fbh[q], &uh, 16);
+        __builtin_memcpy(&fbl[q], &ul, 16);
       }
       for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 4; ++q)
