@@ -46,13 +46,25 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 }
 
 // ---- centre ----------------------------------------------------------------
-// Block of 64 coordinates x 16 row groups: each thread sums every 16th
-// particle of its coordinate (FP64), the 16 partial sums are added in a fixed
+// Block of 32 coordinates x 32 row groups: each thread sums every 32nd
+// particle of its coordinate (FP64), the 32 partial sums are added in a fixed
 // order, and the block then writes the centred columns.  For the diagonal
 // matrix-valued kernel (sq != null) a second pass forms the variance across
 // particles (FP64, ddof 0), q = 1 / var (1 where var = 0), and the BF16 copy
 // used by the Gram is scaled by sqrt(q).
-constexpr int CENTRE_COLS = 64, CENTRE_GROUPS = 16;
+//
+// With CACHE > 0 (X under 4 GiB) a thread keeps its first CACHE values in
+// registers, so that for n <= 32 CACHE the later passes do not read X again.
+// Those values move through raw buffer loads and stores over X, Xc and the
+// BF16 copy: a 32-bit lane offset plus a row offset that is the same for the
+// whole block, and the range check returns 0 for rows past n (and drops
+// their stores).
+constexpr int CENTRE_COLS = 32, CENTRE_GROUPS = 32, CENTRE_CACHE = 64;
+using SvgdRsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ SvgdRsrc svgd_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes), 0x00020000);
+}
+template <int CACHE>
 __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
     const float *x, float *xbar, float *xc, uint16_t *xc16, float *sq, float *vq, int n,
     long long d, uint32_t *status) {
@@ -61,9 +73,27 @@ __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
   const int tx = threadIdx.x % CENTRE_COLS, ty = threadIdx.x / CENTRE_COLS;
   const long long a = (long long)blockIdx.x * CENTRE_COLS + tx;
   const bool in = a < d;
+  const float *xa = x + (in ? a : 0);   // column a (in range even for idle threads)
+  constexpr int NV = CACHE > 0 ? CACHE : 1;
+  float v[NV];
+  const int rest0 = ty + CACHE * CENTRE_GROUPS;   // first row not cached
+  // byte offsets: my element of cached row k is at lb + k rb
+  const uint32_t nbytes = CACHE > 0 ? uint32_t(n) * uint32_t(d) * 4u : 0u;
+  const uint32_t lb = CACHE > 0 ? (uint32_t(ty) * uint32_t(d) + uint32_t(in ? a : 0)) * 4u : 0u;
+  const uint32_t rb = uint32_t(CENTRE_GROUPS) * uint32_t(d) * 4u;
+  if constexpr (CACHE > 0) {
+    const SvgdRsrc rx = svgd_rsrc(x, nbytes);
+#pragma unroll
+    for (int k = 0; k < CACHE; ++k)
+      v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, int(lb), int(k * rb), 0));
+#pragma unroll
+    for (int k = 0; k < CACHE; ++k) v[k] = in ? v[k] : 0.0f;
+  }
   double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < CACHE; ++k) sum += double(v[k]);
   if (in)
-    for (int i = ty; i < n; i += CENTRE_GROUPS) sum += double(x[(long long)i * d + a]);
+    for (int i = rest0; i < n; i += CENTRE_GROUPS) sum += double(xa[(long long)i * d]);
   part[ty][tx] = sum;
   __syncthreads();
   if (ty == 0) {
@@ -81,10 +111,19 @@ __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
   const float m = mean[tx];
   if (sq) {
     double ss = 0.0;
+#pragma unroll
+    for (int k = 0; k < CACHE; ++k) {
+      // an opaque copy, so the FP64 conversions of the first pass are not
+      // kept alive in registers for this one
+      float vk = v[k];
+      asm volatile("" : "+v"(vk));
+      const double dv = double(vk) - double(m);
+      if (ty + k * CENTRE_GROUPS < n) ss += dv * dv;
+    }
     if (in)
-      for (int i = ty; i < n; i += CENTRE_GROUPS) {
-        const double v = double(x[(long long)i * d + a]) - double(m);
-        ss += v * v;
+      for (int i = rest0; i < n; i += CENTRE_GROUPS) {
+        const double dv = double(xa[(long long)i * d]) - double(m);
+        ss += dv * dv;
       }
     __syncthreads();   // every thread has read the means and sums before part is reused
     part[ty][tx] = ss;
@@ -102,11 +141,27 @@ __global__ __launch_bounds__(CENTRE_COLS *CENTRE_GROUPS) void centre_kernel(
   }
   if (!in) return;
   const float sc = scale[tx];
-  for (int i = ty; i < n; i += CENTRE_GROUPS) {
+  if constexpr (CACHE > 0) {
+    const SvgdRsrc r16 = svgd_rsrc(xc16, nbytes / 2u);
+#pragma unroll
+    for (int k = 0; k < CACHE; ++k) {
+      const float c = v[k] - m;
+      __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(sq ? c * sc : c), r16, int(lb / 2u),
+                                            int(k * (rb / 2u)), 0);
+    }
+    if (xc) {
+      const SvgdRsrc rc = svgd_rsrc(xc, nbytes);
+#pragma unroll
+      for (int k = 0; k < CACHE; ++k)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[k] - m), rc, int(lb),
+                                              int(k * rb), 0);
+    }
+  }
+  for (int i = rest0; i < n; i += CENTRE_GROUPS) {
     const long long e = (long long)i * d + a;
-    const float v = x[e] - m;
-    if (xc) xc[e] = v;
-    xc16[e] = f32_to_bf16_rne(sq ? v * sc : v);
+    const float c = x[e] - m;
+    if (xc) xc[e] = c;
+    xc16[e] = f32_to_bf16_rne(sq ? c * sc : c);
   }
 }
 
@@ -1035,8 +1090,13 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
   // the BF16 path without noise never reads the FP32 Xc (it recomputes x - xbar)
   const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
-  centre_kernel<<<dim3(unsigned((d + CENTRE_COLS - 1) / CENTRE_COLS)),
-                  dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(
+  // the register cache addresses X with 32-bit byte offsets, up to row 32 CACHE
+  const unsigned long long rows = (unsigned long long)std::max(n, CENTRE_GROUPS * CENTRE_CACHE);
+  auto *centre = rows * (unsigned long long)d * 4ull < (1ull << 31)
+                     ? centre_kernel<CENTRE_CACHE>
+                     : centre_kernel<0>;
+  centre<<<dim3(unsigned((d + CENTRE_COLS - 1) / CENTRE_COLS)),
+           dim3(CENTRE_COLS * CENTRE_GROUPS), 0, s>>>(
       x, P.xbar, split_update ? nullptr : P.xc, P.xc16, sq, vq, n, d, P.status);
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;

@@ -108,6 +108,30 @@ def test_bf16_path_small_and_ragged_shapes(n, d):
     assert c.poll(ws) == 0
 
 
+@pytest.mark.parametrize("n,d", [(5, 300_001), (2100, 40)])
+def test_centring_beyond_the_register_cache(n, d):
+    """The centring kernel keeps up to 2048 rows per column in registers and
+    addresses X with 32-bit offsets below 2^31 bytes: (5, 300001) exceeds that
+    and takes the instance without the cache; (2100, 40) reads its last 52
+    rows past the cache.  Both with the RBF kernel and with the diagonal
+    matrix-valued kernel (whose variance pass reads the same values)."""
+    g, r, c, ws = _run(n, d, seed=n + d, gram=vb.VIP_GRAM_FP32)
+    errs = dict(D=rel(g["D"], r["D"]), K=rel(g["K"], r["K"]), phi=rel(g["phi"], r["phi"]),
+                X=rel(g["X"], r["X"]))
+    print(f"centring n={n} d={d}: {errs}", flush=True)
+    assert errs["D"] <= 1e-5 and errs["K"] <= 1e-5 and errs["phi"] <= 1e-4 and errs["X"] <= 1e-6
+    assert c.poll(ws) == 0
+    X, G = _ensemble(n, d, seed=n + d + 1)
+    x = dev(X)
+    ws = vb.vip_svgd_step_ex(c, x, dev(G), 50.0, kernel=vb.VIP_KERNEL_DIAG_VAR,
+                             gram_prec=vb.VIP_GRAM_FP32)
+    D, _, _, phi, _ = _inspect(ws, n, d)
+    Xr, info = osvgd.svgd_step_diag(X, G, 50.0)
+    e = dict(D=rel(D, info["D"]), phi=rel(phi, info["phi"]), X=rel(x.cpu().numpy() - X, Xr - X))
+    print(f"centring, diagonal kernel n={n} d={d}: {e}", flush=True)
+    assert e["D"] <= 1e-5 and e["phi"] <= 1e-4 and e["X"] <= 1e-4
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 6])
 def test_median_modes_small_n(n):
     k12 = {vb.VIP_BW_MEDIAN_ALL: 1.0 / 9.0, vb.VIP_BW_MEDIAN_OFFDIAG: 1.0 / 3.0}
