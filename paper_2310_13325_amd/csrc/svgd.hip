@@ -342,24 +342,54 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *xc, const fl
       }
 }
 
-// G = sum_s part[s] in split order; entries of lower blocks mirror the upper ones.
-__global__ void gram_reduce_kernel(const float *part, float *G, int n, int splits) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)n * n) return;
-  int i = int(idx / n), j = int(idx - (long long)i * n);
-  long long src = (i / GB <= j / GB) ? idx : (long long)j * n + i;
-  float s = 0.0f;
-  for (int p = 0; p < splits; ++p) s += part[(long long)p * n * n + src];
-  G[idx] = s;
-}
-
-__global__ void sqdist_kernel(const float *G, float *D, int n, uint32_t *status) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)n * n) return;
-  int i = int(idx / n), j = int(idx - (long long)i * n);
-  float v = (i == j) ? 0.0f : fmaxf(G[(long long)i * n + i] + G[(long long)j * n + j] - 2.0f * G[idx], 0.0f);
-  if (!isfinite(v)) atomicOr(status, VIP_FLAG_NONFINITE);
-  D[idx] = v;
+// Squared distances D_ij = G_ii + G_jj - 2 G_ij (0 on the diagonal, clamped at
+// 0) straight from the Gram partials, G = sum of part[s] in split order.  A
+// block takes a 32 x 32 tile (ti, tj), ti <= tj, which lies in an upper
+// 128 x 128 Gram block, reads its partial rows coalesced, writes its tile of
+// D and, off the diagonal, the mirrored tile through LDS; D is exactly
+// symmetric.
+constexpr int DT = 32;
+__global__ __launch_bounds__(256) void gram_dist_kernel(const float *part, float *D, int n,
+                                                        int splits, int ntile, uint32_t *status) {
+  __shared__ float tile[DT][DT + 1];
+  __shared__ float dg[2][DT];   // G_ii of my rows, G_jj of my columns
+  int ti, tj;
+  upper_block(int(blockIdx.x), ntile, ti, tj);
+  const int i0 = ti * DT, j0 = tj * DT;
+  const long long nn = (long long)n * n;
+  const int t = threadIdx.x;
+  if (t < 2 * DT) {
+    const int k = (t < DT ? i0 : j0) + t % DT;
+    float g = 0.0f;
+    if (k < n)
+      for (int p = 0; p < splits; ++p) g += part[p * nn + (long long)k * n + k];
+    dg[t / DT][t % DT] = g;
+  }
+  __syncthreads();
+  const int c = t % DT, r0 = t / DT;
+  bool bad = false;
+#pragma unroll
+  for (int r = r0; r < DT; r += 256 / DT) {
+    const int i = i0 + r, j = j0 + c;
+    float v = 0.0f;
+    if (i < n && j < n) {
+      float g = 0.0f;
+      for (int p = 0; p < splits; ++p) g += part[p * nn + (long long)i * n + j];
+      v = (i == j) ? 0.0f : fmaxf(dg[0][r] + dg[1][c] - 2.0f * g, 0.0f);
+      bad |= !isfinite(v);
+      D[(long long)i * n + j] = v;
+    }
+    tile[r][c] = v;
+  }
+  if (ti != tj) {
+    __syncthreads();
+#pragma unroll
+    for (int r = r0; r < DT; r += 256 / DT) {
+      const int j = j0 + r, i = i0 + c;
+      if (i < n && j < n) D[(long long)j * n + i] = tile[c][r];
+    }
+  }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
 // ---- exact median by radix select -------------------------------------------
@@ -1084,7 +1114,6 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   ctx->active = ctx->user;
   hipStream_t s = ctx->user;
   const long long nn = (long long)n * n;
-  const unsigned nn_blocks = unsigned((nn + 255) / 256);
 
   const bool diag = kernel == VIP_KERNEL_DIAG_VAR;
   float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
@@ -1106,10 +1135,12 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   else
     gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, sq, P.part, n, d, P.kspan, P.nbt);
   VIP_LAUNCH_CHECK();
-  gram_reduce_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.part, P.G, n, P.splits);
-  VIP_LAUNCH_CHECK();
-  sqdist_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.G, P.D, n, P.status);
-  VIP_LAUNCH_CHECK();
+  {
+    const int ntile = (n + DT - 1) / DT;
+    gram_dist_kernel<<<dim3(unsigned(ntile * (ntile + 1) / 2)), dim3(256), 0, s>>>(
+        P.part, P.D, n, P.splits, ntile, P.status);
+    VIP_LAUNCH_CHECK();
+  }
 
   long long count = 0;
   if (bw_mode != VIP_BW_FIXED) {

@@ -13,7 +13,7 @@ struct SvgdPlan {
   float *xbar = nullptr, *xc = nullptr;
   float *sq = nullptr, *vq = nullptr;   // diagonal kernel: sqrt(q_a), 1 / q_a per coordinate
   uint16_t *xc16 = nullptr;
-  float *part = nullptr, *G = nullptr, *D = nullptr, *K = nullptr, *s = nullptr;
+  float *part = nullptr, *D = nullptr, *K = nullptr, *s = nullptr;
   uint32_t *hist = nullptr, *sel = nullptr;
   double *h2 = nullptr, *L = nullptr;
   float *Lf = nullptr, *xi = nullptr, *phi = nullptr;
@@ -47,7 +47,6 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->xc = A.take<float>(nd);
   P->xc16 = A.take<uint16_t>(nd);
   P->part = A.take<float>(size_t(P->splits) * nn);
-  P->G = A.take<float>(nn);
   P->D = A.take<float>(nn);
   P->K = A.take<float>(nn);
   P->s = A.take<float>(size_t(n));
