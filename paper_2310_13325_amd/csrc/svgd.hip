@@ -394,28 +394,70 @@ __global__ __launch_bounds__(256) void gram_dist_kernel(const float *part, float
 
 // ---- exact median by radix select -------------------------------------------
 // sel[0..2] = (prefix, mask, rank) for target 0, sel[3..5] for target 1.
+// Counts one element of the wave into a 256-bin LDS histogram: the digit of
+// the first counting lane is added once with the number of lanes sharing it
+// (in the first passes most keys share their leading bits, and 64 lanes
+// adding to one bin would serialise), every other counting lane adds its own.
+// Must be reached by the whole wave.
+__device__ __forceinline__ void wave_count(uint32_t *h, bool act, uint32_t digit) {
+  const unsigned long long am = __ballot(act);
+  if (!am) return;
+  const int lane = int(threadIdx.x & 63);
+  const int leader = __ffsll(am) - 1;
+  const uint32_t ld = uint32_t(__shfl(int(digit), leader, 64));
+  const bool same = act && digit == ld;
+  const unsigned long long sm = __ballot(same);
+  if (lane == leader) atomicAdd(&h[ld], uint32_t(__popcll(sm)));
+  if (act && !same) atomicAdd(&h[digit], 1u);
+}
+
+// One pass of the radix select: histogram of the digit at `shift` over the
+// keys (float bits of D >= 0) that match each target's prefix so far.  While
+// the two targets still share their prefix, one histogram serves both.
+// Four consecutive keys per thread (16-byte loads when D is aligned); the
+// loop runs the same number of times on every lane.
 __global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, int offdiag,
-                                                         int shift, const uint32_t *sel,
+                                                         int vec, int shift, const uint32_t *sel,
                                                          uint32_t *hist) {
   __shared__ uint32_t h[2][256];
   for (int b = threadIdx.x; b < 512; b += 256) (&h[0][0])[b] = 0;
   __syncthreads();
   const uint32_t p0 = sel[0], m0 = sel[1], p1 = sel[3], m1 = sel[4];
+  const bool one = p0 == p1 && m0 == m1;
   const long long total = (long long)n * n;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    if (offdiag) {
-      int i = int(idx / n), j = int(idx - (long long)i * n);
-      if (i >= j) continue;
+  const long long groups = (total + 3) / 4;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < groups; base += stride) {
+    const long long g = base + threadIdx.x;
+    const long long e0 = 4 * g;
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (vec && e0 + 3 < total) {
+      const float4 f = *reinterpret_cast<const float4 *>(D + e0);
+      v[0] = f.x;
+      v[1] = f.y;
+      v[2] = f.z;
+      v[3] = f.w;
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q < total) v[q] = D[e0 + q];
     }
-    uint32_t key = __float_as_uint(D[idx]);
-    uint32_t digit = (key >> shift) & 0xFFu;
-    if ((key & m0) == p0) atomicAdd(&h[0][digit], 1u);
-    if ((key & m1) == p1) atomicAdd(&h[1][digit], 1u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long e = e0 + q;
+      bool in = e < total;
+      if (offdiag && in) {
+        const int i = int(e / n), j = int(e - (long long)i * n);
+        in = i < j;
+      }
+      const uint32_t key = __float_as_uint(v[q]);
+      const uint32_t digit = (key >> shift) & 0xFFu;
+      wave_count(h[0], in && (key & m0) == p0, digit);
+      if (!one) wave_count(h[1], in && (key & m1) == p1, digit);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < 512; b += 256) {
-    uint32_t v = (&h[0][0])[b];
+    const uint32_t v = one ? h[0][b & 255] : (&h[0][0])[b];
     if (v) atomicAdd(&hist[b], v);
   }
 }
@@ -1150,11 +1192,12 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     int32_t sel_init[6] = {0, 0, int32_t(r0), 0, 0, int32_t(r1)};
     VIP_TRY(upload_i32(s, reinterpret_cast<int32_t *>(P.sel), sel_init, 6));
     if (count > 0) {
-      unsigned hb = unsigned(std::min<long long>((nn + 255) / 256, 1024));
+      unsigned hb = unsigned(std::min<long long>((nn + 1023) / 1024, 1024));
+      const int vec = reinterpret_cast<uintptr_t>(P.D) % 16 == 0;
       VIP_TRY(fill_u32(s, P.hist, 512, 0u));   // each select clears it for the next pass
       for (int shift = 24; shift >= 0; shift -= 8) {
         radix_hist_kernel<<<dim3(hb), dim3(256), 0, s>>>(P.D, n, bw_mode == VIP_BW_MEDIAN_OFFDIAG,
-                                                         shift, P.sel, P.hist);
+                                                         vec, shift, P.sel, P.hist);
         VIP_LAUNCH_CHECK();
         radix_select_kernel<<<dim3(1), dim3(128), 0, s>>>(P.sel, P.hist, shift);
         VIP_LAUNCH_CHECK();
