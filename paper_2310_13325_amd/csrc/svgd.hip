@@ -183,11 +183,50 @@ __device__ __forceinline__ void upper_block(int u, int nb, int &bi, int &bj) {
 // of each operand; result register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4,
 // column l % 32.
 constexpr int GB = 128;   // block edge
-constexpr int GK = 32;    // k per LDS stage
+constexpr int GK = 64;    // k per LDS stage
 constexpr int GKP = GK + 8;
+constexpr int GIT = GB * GK / 8 / 256;   // 16-byte chunks per thread and operand per stage
 
-__global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, float *part, int n,
-                                                        long long d, long long kspan, int nbt) {
+// One stage of Gram operands into registers: chunk it of thread t is row
+// (t + 256 it) / (GK / 8), k chunk (t + 256 it) % (GK / 8), from rows i0 + row
+// (A) and j0 + row (B, the same as A on a diagonal block).
+__device__ __forceinline__ void gram_load(const uint16_t *xc16, int n, long long d, long long k1,
+                                          int i0, int j0, bool diag, bool vec_ok, long long kb,
+                                          uint4 (&pa)[GIT], uint4 (&pb)[GIT]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < GIT; ++it) {
+    const int idx = t + it * 256;
+    const int row = idx / (GK / 8), ch = idx % (GK / 8);
+    const long long kc = kb + ch * 8;
+    uint4 va = make_uint4(0, 0, 0, 0), vbv = make_uint4(0, 0, 0, 0);
+    if (vec_ok && kc + 8 <= k1) {
+      if (i0 + row < n) va = *reinterpret_cast<const uint4 *>(xc16 + (long long)(i0 + row) * d + kc);
+      if (!diag && j0 + row < n)
+        vbv = *reinterpret_cast<const uint4 *>(xc16 + (long long)(j0 + row) * d + kc);
+    } else {
+      uint32_t ta[4] = {0, 0, 0, 0}, tb[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const long long k = kc + e;
+        const uint32_t a16 = (i0 + row < n && k < k1) ? xc16[(long long)(i0 + row) * d + k] : 0u;
+        const uint32_t b16 = (!diag && j0 + row < n && k < k1) ? xc16[(long long)(j0 + row) * d + k] : 0u;
+        ta[e >> 1] |= a16 << (16 * (e & 1));
+        tb[e >> 1] |= b16 << (16 * (e & 1));
+      }
+      va = make_uint4(ta[0], ta[1], ta[2], ta[3]);
+      vbv = make_uint4(tb[0], tb[1], tb[2], tb[3]);
+    }
+    pa[it] = va;
+    // component-wise, so that the choice is a value select, not a choice of
+    // which local's address to read
+    pb[it] = make_uint4(diag ? va.x : vbv.x, diag ? va.y : vbv.y, diag ? va.z : vbv.z,
+                        diag ? va.w : vbv.w);
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) void gram_bf16_kernel(
+    const uint16_t *xc16, float *part, int n, long long d, long long kspan, int nbt) {
   __shared__ __attribute__((aligned(16))) uint16_t As[GB][GKP];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[GB][GKP];
   const int nup = nbt * (nbt + 1) / 2;
@@ -200,56 +239,56 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const uint16_t *xc16, fl
   int bi, bj;
   upper_block(tb - split * nup, nbt, bi, bj);
   const int i0 = bi * GB, j0 = bj * GB;
+  const bool diag = bi == bj;   // A and B are the same rows
   const long long k0 = (long long)split * kspan;
   const long long k1 = min(d, k0 + kspan);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
   f32x16_t acc[2][2];
+#pragma unroll
   for (int a = 0; a < 2; ++a)
+#pragma unroll
     for (int b = 0; b < 2; ++b)
+#pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
   const bool vec_ok = (d % 8) == 0;
+  // the next stage is prefetched into registers while this one is computed
+  uint4 pa[GIT], pb[GIT];
+  gram_load(xc16, n, d, k1, i0, j0, diag, vec_ok, k0, pa, pb);
   for (long long kb = k0; kb < k1; kb += GK) {
-    for (int it = 0; it < GB * GK / 8 / 256; ++it) {
-      int idx = t + it * 256;
-      int row = idx / (GK / 8), ch = idx % (GK / 8);
-      long long kc = kb + ch * 8;
-      uint4 va = make_uint4(0, 0, 0, 0), vbv = make_uint4(0, 0, 0, 0);
-      if (vec_ok && kc + 8 <= k1) {
-        if (i0 + row < n) va = *reinterpret_cast<const uint4 *>(xc16 + (long long)(i0 + row) * d + kc);
-        if (j0 + row < n) vbv = *reinterpret_cast<const uint4 *>(xc16 + (long long)(j0 + row) * d + kc);
-      } else {
-        uint16_t ta[8], tb[8];
-        for (int e = 0; e < 8; ++e) {
-          long long k = kc + e;
-          ta[e] = (i0 + row < n && k < k1) ? xc16[(long long)(i0 + row) * d + k] : 0;
-          tb[e] = (j0 + row < n && k < k1) ? xc16[(long long)(j0 + row) * d + k] : 0;
-        }
-        __builtin_memcpy(&va, ta, 16);
-        __builtin_memcpy(&vbv, tb, 16);
-      }
-      *reinterpret_cast<uint4 *>(&As[row][ch * 8]) = va;
-      *reinterpret_cast<uint4 *>(&Bs[row][ch * 8]) = vbv;
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+      const int idx = t + it * 256;
+      const int row = idx / (GK / 8), ch = idx % (GK / 8);
+      *reinterpret_cast<uint4 *>(&As[row][ch * 8]) = pa[it];
+      *reinterpret_cast<uint4 *>(&Bs[row][ch * 8]) = pb[it];
     }
     __syncthreads();
+    if (kb + GK < k1) gram_load(xc16, n, d, k1, i0, j0, diag, vec_ok, kb + GK, pa, pb);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 16) {
       bf16x8_t fa[2], fb[2];
+#pragma unroll
       for (int m = 0; m < 2; ++m) {
         uint4 ra = *reinterpret_cast<const uint4 *>(&As[wi * 64 + m * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
         uint4 rb = *reinterpret_cast<const uint4 *>(&Bs[wj * 64 + m * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
         __builtin_memcpy(&fa[m], &ra, 16);
         __builtin_memcpy(&fb[m], &rb, 16);
       }
+#pragma unroll
       for (int m = 0; m < 2; ++m)
+#pragma unroll
         for (int q = 0; q < 2; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fb[q], acc[m][q], 0, 0, 0);
     }
     __syncthreads();
   }
   float *P = part + (long long)split * n * n;
+#pragma unroll
   for (int m = 0; m < 2; ++m)
+#pragma unroll
     for (int q = 0; q < 2; ++q)
+#pragma unroll
       for (int r = 0; r < 16; ++r) {
         int row = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         int col = j0 + wj * 64 + q * 32 + (lane & 31);
