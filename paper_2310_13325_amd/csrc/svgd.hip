@@ -938,30 +938,67 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
 // centring kernel does not store it on this path) and splits it, rows j and
 // j + 1 interleaved as 32-bit pairs (the k order of a matrix-core operand),
 // rows padded with zeros to ldk and columns to dp.
+// Grid: y = pair p, x = 1024 columns per block, four per thread (16-byte
+// loads when d is a multiple of 4, and 16-byte stores: dp is a multiple of 8).
 __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float *x,
                                                     const float *xbar, const float *vq,
                                                     const double *h2,
                                                     uint32_t *bph, uint32_t *bpl, int n,
-                                                    long long d, long long dp, int npairs) {
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long long)npairs * dp) return;
-  const long long a = e % dp;
-  const int p = int(e / dp);
+                                                    long long d, long long dp, int vec) {
+  const int p = int(blockIdx.y);
+  const long long a4 = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;   // my first column
+  if (a4 >= dp) return;
   const float inv_h2 = float(1.0 / h2[0]);
-  uint16_t h[2] = {0, 0}, l[2] = {0, 0};
+  float xb[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sc[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+  const bool full = vec && a4 + 3 < d;
+  if (full) {
+    const float4 t = *reinterpret_cast<const float4 *>(xbar + a4);
+    xb[0] = t.x, xb[1] = t.y, xb[2] = t.z, xb[3] = t.w;
+    if (vq) {
+      const float4 u = *reinterpret_cast<const float4 *>(vq + a4);
+      sc[0] = u.x, sc[1] = u.y, sc[2] = u.z, sc[3] = u.w;
+    }
+  } else {
+    for (int c = 0; c < 4; ++c)
+      if (a4 + c < d) {
+        xb[c] = xbar[a4 + c];
+        if (vq) sc[c] = vq[a4 + c];
+      }
+  }
+  uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int j = 2 * p + q;
-    if (j < n && a < d) {
-      float gv = g[(long long)j * d + a];
-      if (vq) gv *= vq[a];
-      const float xcv = x[(long long)j * d + a] - xbar[a];   // the centring kernel's Xc
-      const float b = fmaf(-xcv, inv_h2, gv);
-      h[q] = f32_to_bf16_rne(b);
-      l[q] = f32_to_bf16_rne(b - bf16_to_f32(h[q]));
+    if (j >= n) continue;
+    float gv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, xv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const long long row = (long long)j * d + a4;
+    if (full) {
+      const float4 tg = *reinterpret_cast<const float4 *>(g + row);
+      const float4 tx = *reinterpret_cast<const float4 *>(x + row);
+      gv[0] = tg.x, gv[1] = tg.y, gv[2] = tg.z, gv[3] = tg.w;
+      xv[0] = tx.x, xv[1] = tx.y, xv[2] = tx.z, xv[3] = tx.w;
+    } else {
+      for (int c = 0; c < 4; ++c)
+        if (a4 + c < d) {
+          gv[c] = g[row + c];
+          xv[c] = x[row + c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (!full && a4 + c >= d) continue;
+      const float gs = vq ? gv[c] * sc[c] : gv[c];
+      const float xcv = xv[c] - xb[c];   // the centring kernel's Xc
+      const float b = fmaf(-xcv, inv_h2, gs);
+      const uint16_t hb = f32_to_bf16_rne(b);
+      const uint16_t lb = f32_to_bf16_rne(b - bf16_to_f32(hb));
+      hw[c] |= uint32_t(hb) << (16 * q);
+      lw[c] |= uint32_t(lb) << (16 * q);
     }
   }
-  bph[e] = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
-  bpl[e] = uint32_t(l[0]) | (uint32_t(l[1]) << 16);
+  const long long o = (long long)p * dp + a4;
+  *reinterpret_cast<uint4 *>(bph + o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+  *reinterpret_cast<uint4 *>(bpl + o) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
 }
 
 // Block: 256 particles x 256 coordinates, 8 waves (4 x 2) of 2 x 4 tiles of
@@ -1200,6 +1237,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
   // the BF16 path without noise never reads the FP32 Xc (it recomputes x - xbar)
   const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
+  if (split_update && (n + 31) / 32 * 16 > 65535) return VIP_E_UNSUPPORTED;   // a grid row per j pair
   // the register cache addresses X with 32-bit byte offsets, up to row 32 CACHE
   const unsigned long long rows = (unsigned long long)std::max(n, CENTRE_GROUPS * CENTRE_CACHE);
   auto *centre = rows * (unsigned long long)d * 4ull < (1ull << 31)
@@ -1275,9 +1313,10 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                     (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
     if (split_update) {
       const int npairs = P.ldk / 2;
-      const long long nb = ((long long)npairs * P.dp + 255) / 256;
-      bpair_kernel<<<dim3(unsigned(nb)), dim3(256), 0, s>>>(g, x, P.xbar, vq, P.h2, P.bph, P.bpl,
-                                                           n, d, P.dp, npairs);
+      const int bvec = d % 4 == 0 && reinterpret_cast<uintptr_t>(g) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(x) % 16 == 0;
+      bpair_kernel<<<dim3(unsigned((P.dp + 1023) / 1024), unsigned(npairs)), dim3(256), 0, s>>>(
+          g, x, P.xbar, vq, P.h2, P.bph, P.bpl, n, d, P.dp, bvec);
       VIP_LAUNCH_CHECK();
       const int vblocks = (n + VM - 1) / VM;
       const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
