@@ -1160,11 +1160,11 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int rb = 0; rb < 16; rb += 4) {
-        const int lr = m * 32 + 8 * (rb >> 2);   // row of r = rb, relative to my first
-        float xv[4][4], si[4];
+      for (int rb = 0; rb < 16; rb += 8) {
+        float xv[8][4], si[8];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
+        for (int rr = 0; rr < 8; ++rr) {
+          const int lr = m * 32 + 8 * ((rb + rr) >> 2) + ((rb + rr) & 3) - rr;
           const int i = i0 + lrow + lr + rr;
           si[rr] = i < n ? s[i] * inv_h2 : 0.0f;
 #pragma unroll
@@ -1174,7 +1174,8 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
           }
         }
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
+        for (int rr = 0; rr < 8; ++rr) {
+          const int lr = m * 32 + 8 * ((rb + rr) >> 2) + ((rb + rr) & 3) - rr;
           if (i0 + lrow + lr + rr >= n) continue;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
