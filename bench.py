@@ -442,12 +442,13 @@ def main():
         Gc = torch.as_tensor(Gn, dtype=torch.float32, device="cuda")
         del Xn, Gn
         svgd = {}
+        reps = 20   # about 25 ms per path: long enough for stable clocks and timing
         for name, prec in (("bf16_gram", vb.VIP_GRAM_BF16), ("fp32_gram", vb.VIP_GRAM_FP32)):
             Xw = Xc.clone()
-            vb.vip_svgd_step(ctx, Xw, Gc, case.eps, gram_prec=prec, ws_tag="c5")
+            for _ in range(3):
+                vb.vip_svgd_step(ctx, Xw, Gc, case.eps, gram_prec=prec, ws_tag="c5")
             torch.cuda.synchronize()
             t = time.perf_counter()
-            reps = 5
             for _ in range(reps):
                 vb.vip_svgd_step(ctx, Xw, Gc, case.eps, gram_prec=prec, ws_tag="c5")
             torch.cuda.synchronize()
@@ -456,7 +457,8 @@ def main():
         Xw = Xc.clone()
         diag = lambda: vb.vip_svgd_step_ex(ctx, Xw, Gc, case.eps, kernel=vb.VIP_KERNEL_DIAG_VAR,
                                            gram_prec=vb.VIP_GRAM_BF16, ws_tag="c5")
-        diag()
+        for _ in range(3):
+            diag()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
