@@ -202,27 +202,54 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Residual rho = (d - dobs)/sigma^2 in place and J = 1/2 sum (d - dobs)^2/sigma^2
 // per pair (FP64, fixed reduction order).
-__global__ __launch_bounds__(256) void residual_kernel(float *d, long long d_stride,
-                                                       const float *dobs, const int *shot_row,
-                                                       int pair0, int ns, long long per_pair,
-                                                       double inv_s2, double *J,
-                                                       uint32_t *status) {
-  __shared__ double part[4];
+// One block of 1024 threads per pair; 16-byte accesses when the rows allow.
+constexpr int RESID_T = 1024;
+__global__ __launch_bounds__(RESID_T) void residual_kernel(float *d, long long d_stride,
+                                                           const float *dobs, const int *shot_row,
+                                                           int pair0, int ns, long long per_pair,
+                                                           double inv_s2, double *J,
+                                                           uint32_t *status) {
+  __shared__ double part[RESID_T / 64];
   const int lp = blockIdx.x;
   const int shot = (pair0 + lp) % ns;
   float *dp = d + lp * d_stride;
   const float *op = dobs + (long long)shot_row[shot] * per_pair;
   double acc = 0.0;
-  for (long long e = threadIdx.x; e < per_pair; e += 256) {
-    double r = double(dp[e]) - double(op[e]);
-    acc += r * r;
-    dp[e] = float(r * inv_s2);
+  const bool vec = per_pair % 4 == 0 &&
+                   ((reinterpret_cast<uintptr_t>(dp) | reinterpret_cast<uintptr_t>(op)) & 15) == 0;
+  if (vec) {
+    float4 *d4 = reinterpret_cast<float4 *>(dp);
+    const float4 *o4 = reinterpret_cast<const float4 *>(op);
+#pragma unroll 4
+    for (long long e = threadIdx.x; e < per_pair / 4; e += RESID_T) {
+      float4 dv = d4[e];
+      const float4 ov = o4[e];
+      const double r0 = double(dv.x) - double(ov.x), r1 = double(dv.y) - double(ov.y);
+      const double r2 = double(dv.z) - double(ov.z), r3 = double(dv.w) - double(ov.w);
+      acc += r0 * r0;
+      acc += r1 * r1;
+      acc += r2 * r2;
+      acc += r3 * r3;
+      dv.x = float(r0 * inv_s2);
+      dv.y = float(r1 * inv_s2);
+      dv.z = float(r2 * inv_s2);
+      dv.w = float(r3 * inv_s2);
+      d4[e] = dv;
+    }
+  } else {
+    for (long long e = threadIdx.x; e < per_pair; e += RESID_T) {
+      const double r = double(dp[e]) - double(op[e]);
+      acc += r * r;
+      dp[e] = float(r * inv_s2);
+    }
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double j = 0.5 * ((part[0] + part[1]) + (part[2] + part[3])) * inv_s2;
+    double t = 0.0;
+    for (int w = 0; w < RESID_T / 64; ++w) t += part[w];
+    const double j = 0.5 * t * inv_s2;
     if (!isfinite(j)) atomicOr(status, VIP_FLAG_NONFINITE);
     J[pair0 + lp] = j;
   }
@@ -242,10 +269,17 @@ __global__ void finalize_grad_kernel(const double *acc64, const float *vel, floa
   int c0 = (ix == 0) ? 0 : nb + ix, c1 = (ix == nx - 1) ? NX - 1 : nb + ix;
   long long N = (long long)NX * NZ;
   double s = 0.0;
-  for (int sh = 0; sh < ns; ++sh) {
-    const double *a = acc64 + ((long long)p * ns + sh) * N;
-    for (int r = r0; r <= r1; ++r)
-      for (int c = c0; c <= c1; ++c) s += a[(long long)r * NX + c];
+  if (r0 == r1 && c0 == c1) {
+    // an interior cell: one padded cell per shot (loads issued together, sum in shot order)
+    const double *a = acc64 + (long long)p * ns * N + (long long)r0 * NX + c0;
+#pragma unroll 5
+    for (int sh = 0; sh < ns; ++sh) s += a[sh * N];
+  } else {
+    for (int sh = 0; sh < ns; ++sh) {
+      const double *a = acc64 + ((long long)p * ns + sh) * N;
+      for (int r = r0; r <= r1; ++r)
+        for (int c = c0; c <= c1; ++c) s += a[(long long)r * NX + c];
+    }
   }
   grad[idx] = float(double(sign) * 2.0 * s / double(vel[idx]));
 }
@@ -858,7 +892,7 @@ vip_status backward_sweep(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, cons
 vip_status launch_residual(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, int pair0,
                            int npairs, const float *dobs, double sigma) {
   long long per_pair = (long long)D.nt * D.nr;
-  residual_kernel<<<dim3(npairs), dim3(256), 0, ctx->s()>>>(
+  residual_kernel<<<dim3(npairs), dim3(RESID_T), 0, ctx->s()>>>(
       P.resid, per_pair, dobs, P.shot_row, pair0, D.ns, per_pair, 1.0 / (sigma * sigma), P.J,
       P.status);
   VIP_LAUNCH_CHECK();

@@ -443,7 +443,7 @@ __device__ __forceinline__ void wave_count(uint32_t *h, bool act, uint32_t digit
   if (!am) return;
   const int lane = int(threadIdx.x & 63);
   const int leader = __ffsll(am) - 1;
-  const uint32_t ld = uint32_t(__shfl(int(digit), leader, 64));
+  const uint32_t ld = uint32_t(__builtin_amdgcn_readlane(int(digit), leader));   // leader is uniform
   const bool same = act && digit == ld;
   const unsigned long long sm = __ballot(same);
   if (lane == leader) atomicAdd(&h[ld], uint32_t(__popcll(sm)));
@@ -453,8 +453,10 @@ __device__ __forceinline__ void wave_count(uint32_t *h, bool act, uint32_t digit
 // One pass of the radix select: histogram of the digit at `shift` over the
 // keys (float bits of D >= 0) that match each target's prefix so far.  While
 // the two targets still share their prefix, one histogram serves both.
-// Four consecutive keys per thread (16-byte loads when D is aligned); the
-// loop runs the same number of times on every lane.
+// Sixteen keys per thread and trip, as four 16-byte loads (when D is
+// aligned) issued before any of them is counted; the loop runs the same
+// number of times on every lane.
+constexpr int RADIX_V = 4;   // 4-key groups per thread and trip
 __global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, int offdiag,
                                                          int vec, int shift, const uint32_t *sel,
                                                          uint32_t *hist) {
@@ -465,33 +467,35 @@ __global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, 
   const bool one = p0 == p1 && m0 == m1;
   const long long total = (long long)n * n;
   const long long groups = (total + 3) / 4;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < groups; base += stride) {
-    const long long g = base + threadIdx.x;
-    const long long e0 = 4 * g;
-    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (vec && e0 + 3 < total) {
-      const float4 f = *reinterpret_cast<const float4 *>(D + e0);
-      v[0] = f.x;
-      v[1] = f.y;
-      v[2] = f.z;
-      v[3] = f.w;
-    } else {
-      for (int q = 0; q < 4; ++q)
-        if (e0 + q < total) v[q] = D[e0 + q];
+  const long long stride = (long long)gridDim.x * blockDim.x * RADIX_V;
+  for (long long base = (long long)blockIdx.x * blockDim.x * RADIX_V; base < groups; base += stride) {
+    float v[RADIX_V][4];
+#pragma unroll
+    for (int u = 0; u < RADIX_V; ++u) {
+      const long long e0 = 4 * (base + u * (long long)blockDim.x + threadIdx.x);
+      if (vec && e0 + 3 < total) {
+        const float4 f = *reinterpret_cast<const float4 *>(D + e0);
+        v[u][0] = f.x, v[u][1] = f.y, v[u][2] = f.z, v[u][3] = f.w;
+      } else {
+        for (int q = 0; q < 4; ++q) v[u][q] = e0 + q < total ? D[e0 + q] : 0.0f;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long long e = e0 + q;
-      bool in = e < total;
-      if (offdiag && in) {
-        const int i = int(e / n), j = int(e - (long long)i * n);
-        in = i < j;
+    for (int u = 0; u < RADIX_V; ++u) {
+      const long long e0 = 4 * (base + u * (long long)blockDim.x + threadIdx.x);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long e = e0 + q;
+        bool in = e < total;
+        if (offdiag && in) {
+          const int i = int(e / n), j = int(e - (long long)i * n);
+          in = i < j;
+        }
+        const uint32_t key = __float_as_uint(v[u][q]);
+        const uint32_t digit = (key >> shift) & 0xFFu;
+        wave_count(h[0], in && (key & m0) == p0, digit);
+        if (!one) wave_count(h[1], in && (key & m1) == p1, digit);
       }
-      const uint32_t key = __float_as_uint(v[q]);
-      const uint32_t digit = (key >> shift) & 0xFFu;
-      wave_count(h[0], in && (key & m0) == p0, digit);
-      if (!one) wave_count(h[1], in && (key & m1) == p1, digit);
     }
   }
   __syncthreads();
@@ -1270,7 +1274,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     int32_t sel_init[6] = {0, 0, int32_t(r0), 0, 0, int32_t(r1)};
     VIP_TRY(upload_i32(s, reinterpret_cast<int32_t *>(P.sel), sel_init, 6));
     if (count > 0) {
-      unsigned hb = unsigned(std::min<long long>((nn + 1023) / 1024, 1024));
+      unsigned hb = unsigned(std::min<long long>((nn + 4095) / 4096, 1024));
       const int vec = reinterpret_cast<uintptr_t>(P.D) % 16 == 0;
       VIP_TRY(fill_u32(s, P.hist, 512, 0u));   // each select clears it for the next pass
       for (int shift = 24; shift >= 0; shift -= 8) {
