@@ -13,7 +13,8 @@
 //   gram        partial Gram blocks of Xc Xc^T over split ranges of d:
 //               BF16 on matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation)
 //               or FP32 on matrix cores (v_mfma_f32_32x32x2_f32)
-//   reduce      G = sum of the partials (fixed order), D_ij = G_ii + G_jj - 2 G_ij
+//   distances   D_ij = G_ii + G_jj - 2 G_ij straight from the partials, G summed
+//               over them in a fixed order (G itself is not stored)
 //   median      exact k-th order statistics of the D values by 4-pass radix
 //               select on their IEEE bits (non-negative floats order like
 //               unsigned integers), then h^2 = med / (2 ln(n+1)) (1 if med = 0)
