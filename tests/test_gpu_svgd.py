@@ -132,6 +132,28 @@ def test_centring_beyond_the_register_cache(n, d):
     assert e["D"] <= 1e-5 and e["phi"] <= 1e-4 and e["X"] <= 1e-4
 
 
+@pytest.mark.parametrize("n", [300, 1025, 2048])
+@pytest.mark.parametrize("dup", [False, True])
+def test_median_exact_at_larger_n(n, dup):
+    """The radix select over many blocks (n^2 keys, an odd n leaving a ragged
+    tail of keys), both median modes, with and without duplicated particles
+    (many equal keys and zeros): h^2 is the median rule applied to the
+    library's own D, bit for bit."""
+    d = 24
+    X, G = _ensemble(n, d, seed=n + 3 * dup)
+    if dup:
+        X[n // 3:] = X[np.arange(n - n // 3) % 7]   # the last two thirds copy the first 7 rows
+    c = ctx()
+    for mode in (vb.VIP_BW_MEDIAN_ALL, vb.VIP_BW_MEDIAN_OFFDIAG):
+        x = dev(X)
+        ws = vb.vip_svgd_step(c, x, dev(G), 1.0, bw_mode=mode, gram_prec=vb.VIP_GRAM_FP32,
+                              ws_tag=f"med{n}")
+        D, _, h2, _, _ = _inspect(ws, n, d)
+        assert np.array_equal(D, D.T) and np.all(np.diag(D) == 0.0)
+        assert h2 == _median_rule(D, n, mode), (mode, h2)
+        assert c.poll(ws) == 0
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 6])
 def test_median_modes_small_n(n):
     k12 = {vb.VIP_BW_MEDIAN_ALL: 1.0 / 9.0, vb.VIP_BW_MEDIAN_OFFDIAG: 1.0 / 3.0}
