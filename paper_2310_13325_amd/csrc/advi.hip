@@ -33,16 +33,17 @@ constexpr int kStepBatch = 8;       // rows whose loads a thread issues together
 
 // ---- full-rank sample ----------------------------------------------------------
 // A block owns kSampleRows consecutive rows and walks their columns up to the
-// last row's diagonal, one column per thread per pass, holding the SG
-// samples' eta of that column in registers, so each L entry is read once per
-// SG samples.  Blocks are numbered from the bottom of the triangle up, so the
+// last row's diagonal, four columns per thread per pass (16-byte loads, with
+// the columns past each row's diagonal masked; one column per pass when L or
+// eta rows are not 16-byte aligned), holding the SG samples' eta of those
+// columns in registers, so each L entry is read once per SG samples.  Blocks are numbered from the bottom of the triangle up, so the
 // longest rows are dispatched first and the short ones fill in behind them.
 // The rows x samples partial sums are reduced across the block in a fixed
 // order.
 template <int SG>
 __global__ __launch_bounds__(kAdviThreads) void advi_sample_full_kernel(
     const float *__restrict__ mu, const float *__restrict__ L, long long ldl,
-    const float *__restrict__ eta, float *__restrict__ theta, long long d, int S) {
+    const float *__restrict__ eta, float *__restrict__ theta, long long d, int S, int vec) {
   __shared__ float red[kAdviThreads / 64][kSampleRows * SG];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s0 = blockIdx.y * SG;
@@ -54,20 +55,49 @@ __global__ __launch_bounds__(kAdviThreads) void advi_sample_full_kernel(
   for (int r = 0; r < kSampleRows; ++r)
 #pragma unroll
     for (int s = 0; s < SG; ++s) acc[r][s] = 0.f;
-  for (long long c = tid; c <= rlast; c += kAdviThreads) {
-    float e[SG];
+  if (vec) {
+    // d and ldl are multiples of 4, so a 4-column group starting at c <= rlast
+    // lies inside every row of L and of eta
+    for (long long c = 4 * tid; c <= rlast; c += 4 * kAdviThreads) {
+      float4 e[SG];
 #pragma unroll
-    for (int s = 0; s < SG; ++s) e[s] = s0 + s < S ? eta[(long long)(s0 + s) * d + c] : 0.f;
-    float v[kSampleRows];
+      for (int s = 0; s < SG; ++s)
+        e[s] = s0 + s < S ? *reinterpret_cast<const float4 *>(eta + (long long)(s0 + s) * d + c)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int r = 0; r < kSampleRows; ++r) {
-      const long long row = r0 + r;
-      v[r] = (row <= rlast && c <= row) ? L[row * ldl + c] : 0.f;
+      for (int r = 0; r < kSampleRows; ++r) {
+        const long long row = r0 + r;
+        float4 v = (row <= rlast && c <= row) ? *reinterpret_cast<const float4 *>(L + row * ldl + c)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        v.y = c + 1 <= row ? v.y : 0.f;   // past the diagonal
+        v.z = c + 2 <= row ? v.z : 0.f;
+        v.w = c + 3 <= row ? v.w : 0.f;
+#pragma unroll
+        for (int s = 0; s < SG; ++s) {
+          float a = acc[r][s];
+          a = fmaf(v.x, e[s].x, a);
+          a = fmaf(v.y, e[s].y, a);
+          a = fmaf(v.z, e[s].z, a);
+          acc[r][s] = fmaf(v.w, e[s].w, a);
+        }
+      }
     }
+  } else {
+    for (long long c = tid; c <= rlast; c += kAdviThreads) {
+      float e[SG];
 #pragma unroll
-    for (int r = 0; r < kSampleRows; ++r)
+      for (int s = 0; s < SG; ++s) e[s] = s0 + s < S ? eta[(long long)(s0 + s) * d + c] : 0.f;
+      float v[kSampleRows];
 #pragma unroll
-      for (int s = 0; s < SG; ++s) acc[r][s] = fmaf(v[r], e[s], acc[r][s]);
+      for (int r = 0; r < kSampleRows; ++r) {
+        const long long row = r0 + r;
+        v[r] = (row <= rlast && c <= row) ? L[row * ldl + c] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < kSampleRows; ++r)
+#pragma unroll
+        for (int s = 0; s < SG; ++s) acc[r][s] = fmaf(v[r], e[s], acc[r][s]);
+    }
   }
 #pragma unroll
   for (int r = 0; r < kSampleRows; ++r)
@@ -257,11 +287,13 @@ extern "C" vip_status vip_advi_sample(vip_ctx *ctx, int32_t family, int64_t d, i
   const long long nb = (d + kSampleRows - 1) / kSampleRows;
   const int sg = S <= kSampleGroup ? pow2_at_least(S) : kSampleGroup;
   const dim3 grid(unsigned(nb), unsigned((S + sg - 1) / sg));
+  const int vec = d % 4 == 0 && ldl % 4 == 0 && reinterpret_cast<uintptr_t>(L) % 16 == 0 &&
+                  reinterpret_cast<uintptr_t>(eta) % 16 == 0;
   switch (sg) {
-    case 1: advi_sample_full_kernel<1><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S); break;
-    case 2: advi_sample_full_kernel<2><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S); break;
-    case 4: advi_sample_full_kernel<4><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S); break;
-    default: advi_sample_full_kernel<8><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S); break;
+    case 1: advi_sample_full_kernel<1><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S, vec); break;
+    case 2: advi_sample_full_kernel<2><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S, vec); break;
+    case 4: advi_sample_full_kernel<4><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S, vec); break;
+    default: advi_sample_full_kernel<8><<<grid, dim3(kAdviThreads), 0, s>>>(mu, L, ldl, eta, theta, d, S, vec); break;
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;
