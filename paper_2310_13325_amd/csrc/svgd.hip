@@ -899,17 +899,19 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
 #pragma unroll
       for (int rb = 0; rb < 16; rb += 4) {
         float xv[4][2], cv[4][2], si[4];
+        // unconditional loads (elements outside the ensemble read element 0
+        // and are never used), so no branch separates them
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
           const int i = i0 + lrow + lr;
-          si[rr] = i < n ? s[i] * inv_h2 : 0.0f;
+          si[rr] = s[i < n ? i : 0];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const bool in = i < n && a0 + lcol + q * 32 < d;
-            const long long e = el + (long long)lr * d + q * 32;
-            xv[rr][q] = in ? x[e] : 0.0f;
-            cv[rr][q] = in ? xc[e] : 0.0f;
+            const long long e = in ? el + (long long)lr * d + q * 32 : 0;
+            xv[rr][q] = x[e];
+            cv[rr][q] = xc[e];
           }
         }
 #pragma unroll
@@ -920,7 +922,7 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
           for (int q = 0; q < 2; ++q) {
             if (a0 + lcol + q * 32 >= d) continue;
             const long long e = el + (long long)lr * d + q * 32;
-            const float p = fmaf(si[rr], cv[rr][q], acc[m][q][r]) * inv_n;
+            const float p = fmaf(si[rr] * inv_h2, cv[rr][q], acc[m][q][r]) * inv_n;
             phi[e] = p;
             float v = xv[rr][q] + eps * p;
             if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
@@ -1146,11 +1148,15 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
         }
       }
   } else {
-    // Plain steps, four rows at a time: every x of the batch is loaded before
-    // any store, so the loads are in flight together (the stores to phi and x
+    // Plain steps in four batches of eight result registers (32 elements):
+    // every x of a batch is loaded before any store (the stores to phi and x
     // could alias them as far as the compiler knows, which would otherwise
-    // serialise each load behind the previous element's stores).  Element
-    // (r, q) of sub-tile m sits at el + (m 32 + 8 (r / 4) + r % 4) d + 32 q.
+    // serialise each load behind the previous element's stores), and the next
+    // batch's loads go out before this batch's stores, since loads and stores
+    // retire through one in-order counter: waiting for loads issued after the
+    // stores would wait for the stores too.  Batch b covers sub-tile b / 2,
+    // registers 8 (b % 2) .. + 7; element (r, q) of sub-tile m sits at
+    // el + (m 32 + 8 (r / 4) + r % 4) d + 32 q.
     const int lrow = wi * 64 + 4 * (lane >> 5);      // my first local row
     const int lcol = wj * 128 + (lane & 31);         // my first local column
     const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
@@ -1162,40 +1168,48 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
       lov[q] = (lo && a < d) ? lo[a] : 0.0f;
       hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
     }
+    // local row (relative to my first) of register r of sub-tile m
+    auto lrow_of = [](int m, int r) { return m * 32 + 8 * (r >> 2) + (r & 3); };
+    float xv[2][8][4], si[2][8];
+    // Loads are unconditional (elements outside the ensemble read x[0] and
+    // s[0] and are never used), so no branch separates them from each other.
+    auto load_batch = [&](int b, float (&xvb)[8][4], float (&sib)[8]) {
+      const int m = b >> 1, rb = (b & 1) * 8;
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+      for (int rr = 0; rr < 8; ++rr) {
+        const int lr = lrow_of(m, rb + rr);
+        const int i = i0 + lrow + lr;
+        sib[rr] = s[i < n ? i : 0];
 #pragma unroll
-      for (int rb = 0; rb < 16; rb += 8) {
-        float xv[8][4], si[8];
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) {
-          const int lr = m * 32 + 8 * ((rb + rr) >> 2) + ((rb + rr) & 3) - rr;
-          const int i = i0 + lrow + lr + rr;
-          si[rr] = i < n ? s[i] * inv_h2 : 0.0f;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const bool in = i < n && a0 + lcol + q * 32 < d;
-            xv[rr][q] = in ? x[el + (long long)(lr + rr) * d + q * 32] : 0.0f;
-          }
-        }
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) {
-          const int lr = m * 32 + 8 * ((rb + rr) >> 2) + ((rb + rr) & 3) - rr;
-          if (i0 + lrow + lr + rr >= n) continue;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (a0 + lcol + q * 32 >= d) continue;
-            const long long e = el + (long long)(lr + rr) * d + q * 32;
-            const float xe = xv[rr][q];
-            const float p = fmaf(si[rr], xe - xb[q], acc[m][q][rb + rr]) * inv_n;
-            phi[e] = p;
-            float v = xe + eps * p;
-            if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
-            bad |= !isfinite(v);
-            x[e] = v;
-          }
+        for (int q = 0; q < 4; ++q) {
+          const bool in = i < n && a0 + lcol + q * 32 < d;
+          xvb[rr][q] = x[in ? el + (long long)lr * d + q * 32 : 0];
         }
       }
+    };
+    load_batch(0, xv[0], si[0]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b + 1 < 4) load_batch(b + 1, xv[(b + 1) & 1], si[(b + 1) & 1]);
+      const int m = b >> 1, rb = (b & 1) * 8;
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int lr = lrow_of(m, rb + rr);
+        if (i0 + lrow + lr >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (a0 + lcol + q * 32 >= d) continue;
+          const long long e = el + (long long)lr * d + q * 32;
+          const float xe = xv[b & 1][rr][q];
+          const float p = fmaf(si[b & 1][rr] * inv_h2, xe - xb[q], acc[m][q][rb + rr]) * inv_n;
+          phi[e] = p;
+          float v = xe + eps * p;
+          if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
+          bad |= !isfinite(v);
+          x[e] = v;
+        }
+      }
+    }
   }
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
