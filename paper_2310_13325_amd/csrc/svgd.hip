@@ -726,7 +726,9 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
   const float inv_n = 1.0f / float(n);
   bool bad = false;
   // All loads first, then the arithmetic and stores (the stores could alias
-  // the loads as far as the compiler knows, which would serialise them).
+  // the loads as far as the compiler knows, which would serialise them); the
+  // loads are unconditional (elements outside the ensemble read element 0 and
+  // are never used), so no branch separates them.
   float xv[4][4], cv[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -734,10 +736,9 @@ __global__ __launch_bounds__(256) void update_kernel(const float *K, const float
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const long long a = a0 + tx * 4 + c;
-      const bool in = i < n && a < d;
-      const long long e = (long long)i * d + a;
-      xv[r][c] = in ? x[e] : 0.0f;
-      cv[r][c] = in ? xc[e] : 0.0f;
+      const long long e = (i < n && a < d) ? (long long)i * d + a : 0;
+      xv[r][c] = x[e];
+      cv[r][c] = xc[e];
     }
   }
 #pragma unroll
