@@ -190,7 +190,8 @@ constexpr int GIT = GB * GK / 8 / 256;   // 16-byte chunks per thread and operan
 
 // One stage of Gram operands into registers: chunk it of thread t is row
 // (t + 256 it) / (GK / 8), k chunk (t + 256 it) % (GK / 8), from rows i0 + row
-// (A) and j0 + row (B, the same as A on a diagonal block).
+// (A) and j0 + row (B; on a diagonal block B is A and is not loaded).  No
+// loaded value is used here, so the loads stay in flight during the stage.
 __device__ __forceinline__ void gram_load(const uint16_t *xc16, int n, long long d, long long k1,
                                           int i0, int j0, bool diag, bool vec_ok, long long kb,
                                           uint4 (&pa)[GIT], uint4 (&pb)[GIT]) {
@@ -219,10 +220,7 @@ __device__ __forceinline__ void gram_load(const uint16_t *xc16, int n, long long
       vbv = make_uint4(tb[0], tb[1], tb[2], tb[3]);
     }
     pa[it] = va;
-    // component-wise, so that the choice is a value select, not a choice of
-    // which local's address to read
-    pb[it] = make_uint4(diag ? va.x : vbv.x, diag ? va.y : vbv.y, diag ? va.z : vbv.z,
-                        diag ? va.w : vbv.w);
+    pb[it] = vbv;   // not loaded on a diagonal block: the store takes pa there
   }
 }
 
@@ -262,7 +260,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
       const int idx = t + it * 256;
       const int row = idx / (GK / 8), ch = idx % (GK / 8);
       *reinterpret_cast<uint4 *>(&As[row][ch * 8]) = pa[it];
-      *reinterpret_cast<uint4 *>(&Bs[row][ch * 8]) = pb[it];
+      const uint4 a = pa[it], b = pb[it];   // component-wise select (a value, not an address)
+      *reinterpret_cast<uint4 *>(&Bs[row][ch * 8]) =
+          make_uint4(diag ? a.x : b.x, diag ? a.y : b.y, diag ? a.z : b.z, diag ? a.w : b.w);
     }
     __syncthreads();
     if (kb + GK < k1) gram_load(xc16, n, d, k1, i0, j0, diag, vec_ok, kb + GK, pa, pb);
