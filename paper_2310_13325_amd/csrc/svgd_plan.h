@@ -28,10 +28,22 @@ struct SvgdPlan {
 
 // Gram blocks are 128 x 128 (upper triangle only); the contraction over d is
 // split so that about 512 workgroups run, each over at least 256 coordinates.
+// Up to twice that many splits are taken when they spread the blocks more
+// evenly over the 256 compute units (all of them are resident at once, so a
+// unit that holds one block more than the others sets the kernel's time).
 inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->nbt = (n + 127) / 128;
   const int nup = P->nbt * (P->nbt + 1) / 2;
   int splits = std::max(1, std::min(64, (512 + nup - 1) / nup));
+  {
+    const int s0 = splits;
+    double best = 0.0;
+    for (int s = s0; s <= std::min(64, 2 * s0); ++s) {
+      const long long b = (long long)nup * s;
+      const double even = double(b) / double(256 * ((b + 255) / 256));
+      if (even > best + 0.02) best = even, splits = s;
+    }
+  }
   long long span = (d + splits - 1) / splits;
   span = (span + 15) / 16 * 16;   // k ranges start on 16-element boundaries (vector loads)
   span = std::max<long long>(256, (span + 63) / 64 * 64);
