@@ -1269,16 +1269,18 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       x, P.xbar, split_update ? nullptr : P.xc, P.xc16, sq, vq, n, d, P.status);
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;
-  dim3 ggrid(unsigned((nup * P.splits + 7) / 8 * 8));
-  if (gram_prec == VIP_GRAM_BF16)
-    gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan, P.nbt);
+  const bool g16 = gram_prec == VIP_GRAM_BF16;
+  const int gsplits = g16 ? P.splits16 : P.splits;
+  dim3 ggrid(unsigned((nup * gsplits + 7) / 8 * 8));
+  if (g16)
+    gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan16, P.nbt);
   else
     gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, sq, P.part, n, d, P.kspan, P.nbt);
   VIP_LAUNCH_CHECK();
   {
     const int ntile = (n + DT - 1) / DT;
     gram_dist_kernel<<<dim3(unsigned(ntile * (ntile + 1) / 2)), dim3(256), 0, s>>>(
-        P.part, P.D, n, P.splits, ntile, P.status);
+        P.part, P.D, n, gsplits, ntile, P.status);
     VIP_LAUNCH_CHECK();
   }
 

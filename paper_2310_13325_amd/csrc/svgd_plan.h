@@ -21,34 +21,39 @@ struct SvgdPlan {
   uint32_t *bph = nullptr, *bpl = nullptr;   // B split, rows (j, j + 1) interleaved, pitch dp
   int ldk = 0;
   long long dp = 0;
-  int nbt = 0, splits = 0;
-  long long kspan = 0;
+  int nbt = 0;
+  int splits = 0, splits16 = 0;        // k splits of the FP32 and of the BF16 Gram
+  long long kspan = 0, kspan16 = 0;    // coordinates per split, same order
   size_t bytes = 0;
 };
 
 // Gram blocks are 128 x 128 (upper triangle only); the contraction over d is
 // split so that about 512 workgroups run, each over at least 256 coordinates.
-// Up to twice that many splits are taken when they spread the blocks more
-// evenly over the 256 compute units (all of them are resident at once, so a
-// unit that holds one block more than the others sets the kernel's time).
+// The FP32 Gram takes up to twice that many splits when they spread the blocks
+// more evenly over the 256 compute units (all of them are resident at once, so
+// a unit that holds one block more than the others sets the kernel's time);
+// the BF16 Gram, six times shorter, keeps the base count, since more partials
+// cost the distance pass more than the balance saves.
 inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->nbt = (n + 127) / 128;
   const int nup = P->nbt * (P->nbt + 1) / 2;
-  int splits = std::max(1, std::min(64, (512 + nup - 1) / nup));
-  {
-    const int s0 = splits;
-    double best = 0.0;
-    for (int s = s0; s <= std::min(64, 2 * s0); ++s) {
-      const long long b = (long long)nup * s;
-      const double even = double(b) / double(256 * ((b + 255) / 256));
-      if (even > best + 0.02) best = even, splits = s;
-    }
+  const int s0 = std::max(1, std::min(64, (512 + nup - 1) / nup));
+  int sb = s0;
+  double best = 0.0;
+  for (int s = s0; s <= std::min(64, 2 * s0); ++s) {
+    const long long b = (long long)nup * s;
+    const double even = double(b) / double(256 * ((b + 255) / 256));
+    if (even > best + 0.02) best = even, sb = s;
   }
-  long long span = (d + splits - 1) / splits;
-  span = (span + 15) / 16 * 16;   // k ranges start on 16-element boundaries (vector loads)
-  span = std::max<long long>(256, (span + 63) / 64 * 64);
-  P->kspan = span;
-  P->splits = int((d + span - 1) / span);
+  auto span_of = [d](int splits) {
+    long long span = (d + splits - 1) / splits;
+    span = (span + 15) / 16 * 16;   // k ranges start on 16-element boundaries (vector loads)
+    return std::max<long long>(256, (span + 63) / 64 * 64);
+  };
+  P->kspan = span_of(sb);
+  P->splits = int((d + P->kspan - 1) / P->kspan);
+  P->kspan16 = span_of(s0);
+  P->splits16 = int((d + P->kspan16 - 1) / P->kspan16);
   const size_t nn = size_t(n) * size_t(n), nd = size_t(n) * size_t(d);
   Arena A;
   A.base = base;
@@ -58,7 +63,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->vq = A.take<float>(size_t(d));
   P->xc = A.take<float>(nd);
   P->xc16 = A.take<uint16_t>(nd);
-  P->part = A.take<float>(size_t(P->splits) * nn);
+  P->part = A.take<float>(size_t(std::max(P->splits, P->splits16)) * nn);
   P->D = A.take<float>(nn);
   P->K = A.take<float>(nn);
   P->s = A.take<float>(size_t(n));
