@@ -29,22 +29,26 @@ struct SvgdPlan {
 
 // Gram blocks are 128 x 128 (upper triangle only); the contraction over d is
 // split so that about 512 workgroups run, each over at least 256 coordinates.
-// The FP32 Gram takes up to twice that many splits when they spread the blocks
-// more evenly over the 256 compute units (all of them are resident at once, so
-// a unit that holds one block more than the others sets the kernel's time);
-// the BF16 Gram, six times shorter, keeps the base count, since more partials
-// cost the distance pass more than the balance saves.
+// Each Gram takes more splits when they spread its blocks more evenly over the
+// 256 compute units (all of them are resident at once, so a unit that holds
+// one block more than the others sets the kernel's time): the FP32 Gram up to
+// twice the base count, the BF16 Gram, six times shorter, up to one and a half
+// times, since every extra partial costs the distance pass a read of n x n.
 inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->nbt = (n + 127) / 128;
   const int nup = P->nbt * (P->nbt + 1) / 2;
   const int s0 = std::max(1, std::min(64, (512 + nup - 1) / nup));
-  int sb = s0;
-  double best = 0.0;
-  for (int s = s0; s <= std::min(64, 2 * s0); ++s) {
-    const long long b = (long long)nup * s;
-    const double even = double(b) / double(256 * ((b + 255) / 256));
-    if (even > best + 0.02) best = even, sb = s;
-  }
+  auto balanced = [nup, s0](int smax) {
+    int sb = s0;
+    double best = 0.0;
+    for (int s = s0; s <= std::min(64, smax); ++s) {
+      const long long b = (long long)nup * s;
+      const double even = double(b) / double(256 * ((b + 255) / 256));
+      if (even > best + 0.02) best = even, sb = s;
+    }
+    return sb;
+  };
+  const int sb = balanced(2 * s0), sb16 = balanced((3 * s0 + 1) / 2);
   auto span_of = [d](int splits) {
     long long span = (d + splits - 1) / splits;
     span = (span + 15) / 16 * 16;   // k ranges start on 16-element boundaries (vector loads)
@@ -52,7 +56,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   };
   P->kspan = span_of(sb);
   P->splits = int((d + P->kspan - 1) / P->kspan);
-  P->kspan16 = span_of(s0);
+  P->kspan16 = span_of(sb16);
   P->splits16 = int((d + P->kspan16 - 1) / P->kspan16);
   const size_t nn = size_t(n) * size_t(n), nd = size_t(n) * size_t(d);
   Arena A;
