@@ -32,8 +32,8 @@ struct SvgdPlan {
 // Each Gram takes more splits when they spread its blocks more evenly over the
 // 256 compute units (all of them are resident at once, so a unit that holds
 // one block more than the others sets the kernel's time): the FP32 Gram up to
-// twice the base count, the BF16 Gram, six times shorter, up to one and a half
-// times, since every extra partial costs the distance pass a read of n x n.
+// four times the base count, the BF16 Gram, six times shorter, up to one and a
+// half times, since every extra partial costs the distance pass a read of n x n.
 inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->nbt = (n + 127) / 128;
   const int nup = P->nbt * (P->nbt + 1) / 2;
@@ -48,7 +48,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
     }
     return sb;
   };
-  const int sb = balanced(2 * s0), sb16 = balanced((3 * s0 + 1) / 2);
+  const int sb = balanced(4 * s0), sb16 = balanced((3 * s0 + 1) / 2);
   auto span_of = [d](int splits) {
     long long span = (d + splits - 1) / splits;
     span = (span + 15) / 16 * 16;   // k ranges start on 16-element boundaries (vector loads)
