@@ -39,13 +39,26 @@ HBM_PEAK_GBS = 8000.0
 # disables: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 ALU_PEAK_TFLOPS = 78.6
 ALU_PUBLISHED_TFLOPS = 157.3
-# Algorithmic HBM bytes per padded grid point per pair per time step (a
-# "point-step"), the per-unit figures of a streaming sweep in the increment
-# form: read u, q, c and write u, q (20 B); the recompute also stores
-# a^n = L u^n + f^n (4 B), the adjoint reads it back (4 B).  Over the three
-# sweeps this is 68 B per point-step and shot.
+# Streaming-equivalent HBM bytes per padded grid point per pair per time step
+# (a "point-step"): what a sweep that keeps nothing on chip moves in the
+# increment form -- read u, q, c and write u, q (20 B); the recompute also
+# stores a^n = L u^n + f^n (4 B), the adjoint reads it back (4 B); 68 B per
+# point-step and shot over the three sweeps.  A temporally blocked kernel moves
+# less, so this figure is reported as a rate only, never as a roofline fraction.
 BYTES_PER_POINT_STEP = {"forward": 20.0, "recompute": 24.0, "adjoint": 24.0,
                         "forward_store": 24.0}
+# Compulsory HBM bytes of the blocked schedule, the roofline's per-unit figures:
+# per padded point, pair and launch the state u, q and the coefficient c are
+# read once (12 B) and u, q written once (8 B); the adjoint also adds its
+# launch's imaging partial into the FP64 sum (8 B read + 8 B write); per
+# point-step the modes that keep a^n store it (4 B) and the adjoint reads it (4 B).
+COMPULSORY_PER_POINT_LAUNCH = {"forward": 20.0, "recompute": 20.0, "adjoint": 36.0,
+                               "forward_store": 20.0}
+COMPULSORY_PER_POINT_STEP = {"forward": 0.0, "recompute": 4.0, "adjoint": 4.0,
+                             "forward_store": 4.0}
+# VALU issue peak: one wave64 VALU instruction per SIMD every 4 cycles (16 lanes),
+# 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave-instructions per second.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 # Algorithmic flops per point-step: the fourth-order Laplacian with symmetric
 # weights (4 pair sums, 1 centre product, 4 fused multiply-adds = 13), the
 # increment update q' = g (q + c L u), u' = g u + q' (5); the adjoint adds the
@@ -81,7 +94,7 @@ def traffic_from_counters(configuration: dict):
         return None
     if c.get("source_sha256_16") != source_hash() or c.get("configuration") != configuration:
         return None
-    return c.get("traffic_bytes_per_launch")
+    return c
 
 
 def setup(prob, ctx, vb, synth, torch, npart):
@@ -102,9 +115,10 @@ def setup(prob, ctx, vb, synth, torch, npart):
                 sigma=sigma, v_true=v, lo_np=lo, hi_np=hi, parts=parts)
 
 
-def cpu_baseline(prob, S, ctx, vb, torch, workers):
+def cpu_baseline(prob, S, ctx, vb, torch, workers, sched):
     """The FP64 oracle (a process per shot) on one particle of the workload,
-    plus the GPU's error against it on the same inputs."""
+    plus the GPU's error against it on the same inputs, the GPU run in the
+    timed configuration (the context's tile, the timed memory schedule)."""
     import numpy as np
     from oracle import cpu_pool
     from oracle import fwi as ofwi
@@ -123,7 +137,8 @@ def cpu_baseline(prob, S, ctx, vb, torch, workers):
     wall = time.perf_counter() - t0
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
     lp, g = vb.vip_grad_logpost(ctx, S["grid"], S["geom"], f32(part), f32(dobs), sigma,
-                                ckpt_every=prob.ckpt_every, ws_tag="err")
+                                ckpt_every=prob.ckpt_every, stored_steps=sched["stored_steps"],
+                                live_pairs=sched["live_pairs"], ws_tag="err")
     g = g.cpu().numpy().astype(np.float64)
     err_g = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     err_lp = float(abs(lp.cpu().numpy()[0] - lp_ref[0]) / abs(lp_ref[0]))
@@ -150,7 +165,8 @@ def cpu_baseline(prob, S, ctx, vb, torch, workers):
             "sample_1core": f"shot 0 of the same particle in one process ({one_shot:.1f} s), "
                             f"times {prob.ns} shots",
             "cpu_model": model}
-    err = {"grad_rel_l2": err_g, "logpost_rel": err_lp, "against": "FP64 oracle, 1 particle"}
+    err = {"grad_rel_l2": err_g, "logpost_rel": err_lp,
+           "against": "FP64 oracle, 1 particle, the timed tile and memory schedule"}
     return base, err
 
 
@@ -228,6 +244,156 @@ def advi_rates(prob, S, ctx, vb, torch, sched):
     return out
 
 
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def c1_rate(ctx, vb, synth, torch, configs):
+    """c1: the plain SVGD-FWI loop, 8 particles x 4 shots on 64 x 64 cells,
+    nt = 500: 20 iterations of the gradients plus an SVGD step (FP32 Gram,
+    median bandwidth, clip)."""
+    prob = configs.C1
+    S1 = setup(prob, ctx, vb, synth, torch, prob.np)
+    n, d = prob.np, prob.d
+    X = S1["x"].view(n, d)
+    lp = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(S1["x"])
+    eps = {}
+
+    def run():
+        for _ in range(configs.SVGD_STEPS_C1):
+            vb.vip_grad_logpost(ctx, S1["grid"], S1["geom"], S1["x"], S1["dobs"], S1["sigma"],
+                                ckpt_every=prob.ckpt_every, lo=S1["lo"], hi=S1["hi"],
+                                logpost=lp, grad=g, ws_tag="c1")
+            if "eps" not in eps:
+                eps["eps"] = 10.0 / float(g.abs().max())
+            vb.vip_svgd_step(ctx, X, g.view(n, d), eps["eps"], gram_prec=vb.VIP_GRAM_FP32,
+                             lo=S1["lo"].view(-1), hi=S1["hi"].view(-1), ws_tag="c1svgd")
+
+    sec = _timed(torch, run, 3)
+    ctx._ws.pop("c1", None)
+    ctx._ws.pop("c1svgd", None)
+    steps = configs.SVGD_STEPS_C1
+    return {"workload": "c1: 64x64 at 10 m, nt=500, 4 shots, 64 receivers, 8 particles, "
+                        f"{steps} SVGD iterations (gradients + FP32-Gram SVGD step)",
+            "svgd_iterations_per_s": round(steps / sec, 1),
+            "particle_gradients_per_s": round(steps * n / sec, 1), "tile": ctx.tile_for(S1["grid"])}
+
+
+def c3_rate(ctx, vb, synth, torch, configs, autotune):
+    """c3: 64 particles x 20 shots on 400 x 200 cells at 12.5 m, nt = 4000:
+    particle-gradients/s with the tile and memory schedule (checkpoint
+    interval 50, stored tail steps, live pairs) picked by the autotuner."""
+    prob = configs.C3
+    S3 = setup(prob, ctx, vb, synth, torch, prob.np)
+    n = prob.np
+    lp = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(S3["x"])
+    fn = lambda st, live: vb.vip_grad_logpost(
+        ctx, S3["grid"], S3["geom"], S3["x"], S3["dobs"], S3["sigma"], ckpt_every=prob.ckpt_every,
+        lo=S3["lo"], hi=S3["hi"], logpost=lp, grad=g, stored_steps=st, live_pairs=live,
+        ws_tag="c3")
+    torch.cuda.empty_cache()
+    budget = int(torch.cuda.mem_get_info()[0] + ctx.workspace_bytes() - 8e9)
+    cands = autotune.schedules(S3["grid"], S3["geom"], n, prob.ckpt_every, budget)
+    tile, st, live, tm = autotune.tune_joint(ctx, fn, cands, tiles=[0, 2])
+    ctx.read_timing()
+    ctx.set_timing(True)
+    sec = _timed(torch, lambda: fn(st, live), 2)
+    ctx.set_timing(False)
+    timing = ctx.read_timing()
+    ctx._ws.pop("c3", None)
+    torch.cuda.empty_cache()
+    npts = (prob.nx + 2 * prob.nb) * (prob.nz + 2 * prob.nb)
+    modes = {k: {"launches": t["launches"],
+                 "avg_launch_us": round(t["ms"] * 1e3 / t["launches"], 2)}
+             for k, t in timing.items() if t["launches"]}
+    return {"workload": "c3: 400x200 at 12.5 m + 20-cell sponge, nt=4000, dt=1 ms, 20 shots, "
+                        "400 receivers, 10 Hz Ricker, 64 particles, checkpoints every 50 steps",
+            "value": round(n / sec, 3), "unit": "particle-gradients/s",
+            "ms_per_call": round(sec * 1e3, 1), "tile": tile, "stored_steps": st,
+            "live_pairs": live, "schedules": [list(c) for c in cands], "modes": modes,
+            # a streaming sweep (68 B per point-step and shot) at the HBM peak
+            "streaming_ceiling_pg_per_s": round(
+                HBM_PEAK_GBS * 1e9 / (68.0 * prob.ns * (prob.nt - 1) * npts), 2)}, S3
+
+
+def c3_err(prob, S3, ctx, vb, torch, workers, sched):
+    """The c3 gradient of one particle in the timed configuration against the
+    FP64 C oracle (observed data from the oracle on the true model)."""
+    import numpy as np
+    from oracle import cref
+    from oracle import fwi as ofwi
+    from paper_2310_13325_amd import synth
+    grid = ofwi.Grid(nz=prob.nz, nx=prob.nx, nb=prob.nb, nt=prob.nt, dx=prob.dx, dz=prob.dx,
+                     dt=prob.dt, alpha=prob.alpha)
+    geom = ofwi.Geometry(src_iz=(prob.src_iz,) * prob.ns, src_ix=prob.src_ix,
+                         rec_iz=(prob.rec_iz,) * prob.nr, rec_ix=prob.rec_ix, f0=prob.f0)
+    v_true = np.float32(S3["v_true"]).astype(np.float64)
+    clean = cref.simulate(v_true, grid, geom, workers=workers)
+    sigma = 0.02 * float(np.median(np.abs(clean).max(axis=1)))
+    dobs = np.float32(clean + sigma * synth.noise(prob)).astype(np.float64)
+    part = np.float32(S3["parts"][:1]).astype(np.float64)
+    lp_ref, g_ref = cref.grad_logpost(part, grid, geom, dobs, sigma, workers=workers)
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    ctx.set_tile(sched["tile"])
+    lp, g = vb.vip_grad_logpost(ctx, S3["grid"], S3["geom"], f32(part), f32(dobs), sigma,
+                                ckpt_every=prob.ckpt_every, stored_steps=sched["stored_steps"],
+                                live_pairs=sched["live_pairs"], ws_tag="c3err")
+    g = g.cpu().numpy().astype(np.float64)
+    ctx._ws.pop("c3err", None)
+    return {"grad_rel_l2": float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)),
+            "logpost_rel": float(abs(lp.cpu().numpy()[0] - lp_ref[0]) / abs(lp_ref[0])),
+            "against": "FP64 C oracle, 1 particle, the timed tile and memory schedule"}
+
+
+def c4_rates(ctx, vb, synth, torch, configs, autotune):
+    """c4: three inversions of uneven size (96x96, 150x100, 256x128; nt 800,
+    1200, 1600; 4, 6, 8 shots; 32 particles each) in merged launches against
+    the three run one after the other, plus the batched sSVGD step (FP64
+    Cholesky of each 32 x 32 kernel matrix)."""
+    Ss = [setup(p, ctx, vb, synth, torch, p.np) for p in configs.C4]
+    probs = [vb.Problem(S["grid"], S["geom"], S["x"], S["dobs"], S["sigma"], lo=S["lo"], hi=S["hi"])
+             for S in Ss]
+    key = autotune.key_for_batch(probs)
+    tile = autotune.tune(ctx, lambda: vb.vip_grad_logpost_multi(ctx, probs, ckpt_every=50), key,
+                         tiles=range(vb.lib().vip_tile_count()))
+    batched = _timed(torch, lambda: vb.vip_grad_logpost_multi(ctx, probs, ckpt_every=50), 3)
+    ctx.set_tile(-2)
+
+    def one_by_one():
+        for k, (S, p) in enumerate(zip(Ss, configs.C4)):
+            vb.vip_grad_logpost(ctx, S["grid"], S["geom"], S["x"], S["dobs"], S["sigma"],
+                                ckpt_every=50, lo=S["lo"], hi=S["hi"], logpost=probs[k].logpost,
+                                grad=probs[k].grad, ws_tag=f"c4_{k}")
+
+    separate = _timed(torch, one_by_one, 3)
+    xs = [S["x"].view(p.np, p.d) for S, p in zip(Ss, configs.C4)]
+    gs = [pr.grad.view(p.np, p.d) for pr, p in zip(probs, configs.C4)]
+    eps = [10.0 / float(g.abs().max()) for g in gs]
+    los = [S["lo"].view(-1) for S in Ss]
+    his = [S["hi"].view(-1) for S in Ss]
+    svgd = _timed(torch, lambda: vb.vip_ssvgd_step_multi(ctx, xs, gs, eps, seed=4, lo=los, hi=his,
+                                                         gram_prec=vb.VIP_GRAM_FP32), 5)
+    for k in range(3):
+        ctx._ws.pop(f"c4_{k}", None)
+    ctx._ws.pop("multi", None)
+    ctx._ws.pop("svgd_multi", None)
+    total = sum(p.np for p in configs.C4)
+    return {"workload": "c4: 96x96 / 150x100 / 256x128 at 10 m, nt 800/1200/1600, 4/6/8 shots, "
+                        "32 particles each",
+            "batched_pg_per_s": round(total / batched, 1), "tile": tile,
+            "one_by_one_pg_per_s": round(total / separate, 1),
+            "batched_vs_one_by_one": round(separate / batched, 3),
+            "ssvgd_multi_steps_per_s": round(1.0 / svgd, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +405,8 @@ def main():
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-minibatch", action="store_true")
     ap.add_argument("--no-advi", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the c1, c3 and c4 workload rates")
     ap.add_argument("--graph", action="store_true", help="replay the gradient through a hipGraph")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile shape (no tile tuning)")
     ap.add_argument("--stored-steps", type=int, default=None,
@@ -356,29 +524,52 @@ def main():
                  f"up to {sh['tmax']} steps per launch)")
     else:
         kname = "fd_step (one step per launch)"
+    # pairs each launch advances: the live pairs of a chunk (equal chunks but
+    # possibly a shorter last one; every chunk runs the same launches)
+    pairs = n * prob.ns
+    live = sched["live_pairs"] or pairs
+    nchunks = -(-pairs // live)
+    npts = (prob.nx + 2 * prob.nb) * (prob.nz + 2 * prob.nb)
     kinds = {}
     for k, t in timing.items():
         if t["launches"]:
             per_launch_s = t["ms"] * 1e-3 / t["launches"]
             ps = t["point_steps"] / t["launches"]
+            # pair-points per launch, averaged over the chunks (each chunk runs
+            # the same number of launches)
+            pl = pairs * npts / nchunks
+            comp = COMPULSORY_PER_POINT_LAUNCH[k] * pl + COMPULSORY_PER_POINT_STEP[k] * ps
             kinds[k] = {"launches": t["launches"], "avg_launch_us": round(per_launch_s * 1e6, 2),
                         "point_steps_per_launch": ps,
-                        "alg_GBps": round(BYTES_PER_POINT_STEP[k] * ps / per_launch_s / 1e9, 1),
+                        "compulsory_bytes_per_launch": int(comp),
+                        "compulsory_GBps": round(comp / per_launch_s / 1e9, 1),
+                        "streaming_equivalent_GBps": round(
+                            BYTES_PER_POINT_STEP[k] * ps / per_launch_s / 1e9, 1),
                         "alg_TFLOPs": round(FLOPS_PER_POINT_STEP[k] * ps / per_launch_s / 1e12, 3),
                         "share_of_step": round(t["ms"] / 1e3 / (elapsed / args.steps * timed_calls), 3)}
     dom = max(kinds, key=lambda k: kinds[k]["share_of_step"])
-    ach = kinds[dom]["alg_GBps"]
-    traffic = traffic_from_counters({"tile": tile, "stored_steps": sched["stored_steps"],
-                                     "live_pairs": sched["live_pairs"]})
-    tr = None if traffic is None else traffic.get(dom)
-    meas = None if tr is None else round(tr / (kinds[dom]["avg_launch_us"] * 1e-6) / 1e9, 1)
+    ach = kinds[dom]["compulsory_GBps"]
+    counters = traffic_from_counters({"tile": tile, "stored_steps": sched["stored_steps"],
+                                      "live_pairs": sched["live_pairs"]})
+    tr = None if counters is None else counters.get("traffic_bytes_per_launch", {}).get(dom)
+    vi = None if counters is None else counters.get("valu_instr_per_launch", {}).get(dom)
+    launch_s = kinds[dom]["avg_launch_us"] * 1e-6
+    meas = None if tr is None else round(tr / launch_s / 1e9, 1)
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": tr,
+                "bytes_model": "compulsory bytes of the blocked schedule per launch: "
+                               "(u, q, c read + u, q written: 20 B; adjoint +16 B FP64 imaging "
+                               "read-modify-write) per padded point and pair, plus 4 B of a^n "
+                               "per point-step",
                 # counter-measured HBM bytes per launch over the live launch time
                 "measured_GBps": meas,
                 "measured_frac": None if meas is None else round(meas / HBM_PEAK_GBS, 4),
                 "kernel": f"{kname}, {dom} mode", "modes": kinds,
+                # VALU issue rate from the counted wave instructions (SQ_INSTS_VALU)
+                "valu": None if vi is None else {
+                    "achieved": round(vi / launch_s / 1e9, 1), "peak": VALU_ISSUE_PEAK / 1e9,
+                    "unit": "G wave-instr/s", "frac": round(vi / launch_s / VALU_ISSUE_PEAK, 4)},
                 "alu": {"achieved": kinds[dom]["alg_TFLOPs"], "peak": ALU_PEAK_TFLOPS,
                         "unit": "TFLOP/s",
                         "frac": round(kinds[dom]["alg_TFLOPs"] / ALU_PEAK_TFLOPS, 4),
@@ -419,6 +610,22 @@ def main():
     if not args.no_advi:
         extra["advi"] = advi_rates(prob, S, ctx, vb, torch, sched)
         log(f"advi: {extra['advi']}")
+    main_tile = ctx.tile_for(S["grid"])
+    S3 = sched3 = None
+    if not args.no_workloads:
+        ctx._ws.pop("grad", None)
+        torch.cuda.empty_cache()
+        work = {}
+        work["c1"] = c1_rate(ctx, vb, synth, torch, configs)
+        log(f"c1: {work['c1']}")
+        work["c4"] = c4_rates(ctx, vb, synth, torch, configs, autotune)
+        log(f"c4: {work['c4']}")
+        work["c3"], S3 = c3_rate(ctx, vb, synth, torch, configs, autotune)
+        sched3 = {"tile": work["c3"]["tile"], "stored_steps": work["c3"]["stored_steps"],
+                  "live_pairs": work["c3"]["live_pairs"]}
+        log(f"c3: {work['c3']}")
+        extra["workloads"] = work
+        ctx.set_tile(main_tile)
     if not args.no_plain:
         x1 = S["x"][:1].contiguous()
         vb.vip_grad_logpost_plain(ctx, S["grid"], S["geom"], x1, S["dobs"], S["sigma"],
@@ -485,7 +692,12 @@ def main():
         from oracle import cpu_pool
         workers = min(cpu_pool.default_workers(), prob.ns)
         log(f"cpu baseline on {workers} cores")
-        cpu, err = cpu_baseline(prob, S, ctx, vb, torch, workers)
+        cpu, err = cpu_baseline(prob, S, ctx, vb, torch, workers, sched)
+        if S3 is not None:
+            extra["workloads"]["c3"]["err"] = c3_err(configs.C3, S3, ctx, vb, torch,
+                                                     cpu_pool.default_workers(), sched3)
+            ctx.set_tile(main_tile)
+            log(f"c3 err: {extra['workloads']['c3']['err']}")
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "particle-gradients/s",
@@ -494,7 +706,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": "c2: FP32 batched gradients + sSVGD step; 200x120 grid at 20 m "
                                "+ 20-cell sponge, nt=2000, dt=2 ms, 10 shots, 200 receivers, "
-                               "8 Hz Ricker, 128 particles, checkpoints every 50 steps",
+                               "8 Hz Ricker, 128 particles; memory schedule as tuned "
+                               "(stored_steps a^n kept by the forward sweep, the rest "
+                               "checkpointed every 50 steps)",
                    "particles": n, "pairs_per_step": n * prob.ns, "graph": args.graph,
                    "gram": "bf16", "parallelism": "1 GPU", "tile": ctx.tile_for(S["grid"]),
                    "stored_steps": sched["stored_steps"], "live_pairs": sched["live_pairs"]},

@@ -88,8 +88,9 @@ typedef struct {
  * shot_index (host [ns], or NULL for 0 .. ns-1) names the row of the observed
  * data holding each listed shot, and nobs the number of rows (0 .. nobs-1;
  * ignored when shot_index is NULL).  A geometry listing a random subset of a
- * survey's shots, read in place from the full d_obs, gives the minibatch
- * gradients of section 2.4 (with sigma scaled as in vip_grad_logpost). */
+ * survey's nobs shots, read in place from the full d_obs, gives the minibatch
+ * gradients of section 2.4: vip_grad_logpost then scales the misfit of the
+ * listed shots by nobs / ns itself (see there). */
 typedef struct {
   int32_t ns;
   const int32_t *src_ix, *src_iz;
@@ -138,8 +139,9 @@ vip_status vip_destroy(vip_ctx *ctx);
 vip_status vip_set_stream(vip_ctx *ctx, void *stream);
 /* Graph mode: when on, vip_grad_logpost / vip_forward capture their whole
  * launch sequence into a hipGraph the first time they see a given argument
- * set and replay it afterwards (the arguments, including pointers, form the
- * cache key).  Off by default. */
+ * set and replay it afterwards (the arguments, including pointers and the
+ * geometry's tables, form the cache key; a context keeps the 32 most recent
+ * graphs, evicting the oldest after its replays finish).  Off by default. */
 vip_status vip_set_graph_mode(vip_ctx *ctx, int enable);
 /* Shape of the time-stepping kernel.  tile = -2 (default) picks a shape per
  * grid; -1 advances one step per launch (each block a 64 x 4*rz tile with its
@@ -226,14 +228,19 @@ vip_status vip_grad_logpost_workspace(const vip_grid *grid, const vip_geometry *
  * dropped), and grad[p] = d logpost / d vel[p], obtained by the adjoint-state
  * method (section 3) on the exact discrete adjoint of the forward scheme:
  * forward sweep with checkpoints, then per segment a recompute sweep and an
- * adjoint sweep with the imaging sum accumulated in FP64 across segments and
- * shots.
+ * adjoint sweep with the imaging sum accumulated in FP64 (each launch of the
+ * step kernel adds its FP32 partial over at most 8 steps) and summed over the
+ * shots in FP64.
  * dobs: device float [ns][nt][nr] (or [nobs][nt][nr] read through the
  * geometry's shot_index).  logpost: device double [np].
  * grad: device float [np][nz][nx].  prior may be NULL (no prior).
- * Minibatch (section 2.4, uniformly random data subsets): for b of a survey's
- * S shots, sigma * sqrt(b / S) makes J the unbiased estimate (S / b) sum over
- * the subset of the per-shot misfits, and its gradient likewise. */
+ * Minibatch (section 2.4, uniformly random data subsets): when the geometry
+ * carries a shot_index, its ns listed shots are taken as a subset of the
+ * nobs shots of dobs and J is the unbiased estimate
+ *   J = (nobs / ns) 1/2 sum_{listed s, n, r} (d - dobs)^2 / sigma^2,
+ * whose expectation over uniformly drawn subsets is the full-survey misfit;
+ * the residual and the gradient carry the same factor.  sigma is the
+ * survey's own noise level (no caller-side scaling). */
 vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geometry *geom,
                             const vip_prior *prior, int32_t np, const float *vel,
                             const float *dobs, double sigma, int32_t ckpt_every,

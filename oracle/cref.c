@@ -81,9 +81,11 @@ static void release(problem *P) {
   free(P->g);
 }
 
-/* Forward of one shot.  traces [nt][nr]; hist (optional) [nt-1][N] = L u^n + f^n. */
+/* Forward of one shot.  traces [nt][nr]; hist (optional) [nt-1][N] = L u^n + f^n;
+ * snaps (optional) [nsnap][N] = u^n at the steps snap_n[k], ascending. */
 static int forward(const problem *P, int src_iz, int src_ix, int nr, const int *rec_iz,
-                   const int *rec_ix, const double *wavelet, double *traces, double *hist) {
+                   const int *rec_ix, const double *wavelet, double *traces, double *hist,
+                   int nsnap, const int *snap_n, double *snaps) {
   const int NZ = P->NZ, NX = P->NX;
   const size_t N = (size_t)NZ * NX;
   double *um = calloc(N, sizeof(double)), *u = calloc(N, sizeof(double));
@@ -93,6 +95,8 @@ static int forward(const problem *P, int src_iz, int src_ix, int nr, const int *
   const int s = (src_iz + P->nb) * NX + src_ix + P->nb;
   const double area = P->dx * P->dz;
   for (int r = 0; r < nr; ++r) traces[r] = 0.0;
+  int ks = 0;
+  while (ks < nsnap && snap_n[ks] == 0) memset(snaps + (size_t)ks++ * N, 0, N * sizeof(double));
   for (int n = 0; n <= P->nt - 2; ++n) {
     laplacian(u, a, pad, NZ, NX, P->dz, P->dx);
     a[s] += wavelet[n] / area;
@@ -101,6 +105,7 @@ static int forward(const problem *P, int src_iz, int src_ix, int nr, const int *
     for (int r = 0; r < nr; ++r)
       traces[(size_t)(n + 1) * nr + r] = up[(rec_iz[r] + P->nb) * NX + rec_ix[r] + P->nb];
     if (hist) memcpy(hist + (size_t)n * N, a, N * sizeof(double));
+    while (ks < nsnap && snap_n[ks] == n + 1) memcpy(snaps + (size_t)ks++ * N, up, N * sizeof(double));
     double *t = um;
     um = u;
     u = up;
@@ -116,7 +121,23 @@ int cref_shot_forward(int nz, int nx, int nb, int nt, double dx, double dz, doub
                       double *traces) {
   problem P;
   if (setup(&P, nz, nx, nb, nt, dx, dz, dt, alpha, vel)) return -1;
-  int st = forward(&P, src_iz, src_ix, nr, rec_iz, rec_ix, wavelet, traces, NULL);
+  int st = forward(&P, src_iz, src_ix, nr, rec_iz, rec_ix, wavelet, traces, NULL, 0, NULL, NULL);
+  release(&P);
+  return st;
+}
+
+/* Wavefields u^n [nsnap][NZ][NX] of one shot at the steps snap_n (ascending,
+ * 0 <= n <= nt-1), and its traces [nt][nr]. */
+int cref_shot_snapshots(int nz, int nx, int nb, int nt, double dx, double dz, double dt,
+                        double alpha, const double *vel, int src_iz, int src_ix, int nr,
+                        const int *rec_iz, const int *rec_ix, const double *wavelet,
+                        int nsnap, const int *snap_n, double *snaps, double *traces) {
+  for (int k = 0; k < nsnap; ++k)
+    if (snap_n[k] < 0 || snap_n[k] > nt - 1 || (k > 0 && snap_n[k] <= snap_n[k - 1])) return -2;
+  problem P;
+  if (setup(&P, nz, nx, nb, nt, dx, dz, dt, alpha, vel)) return -1;
+  int st = forward(&P, src_iz, src_ix, nr, rec_iz, rec_ix, wavelet, traces, NULL, nsnap, snap_n,
+                   snaps);
   release(&P);
   return st;
 }
@@ -133,7 +154,8 @@ int cref_shot_gradient(int nz, int nx, int nb, int nt, double dx, double dz, dou
   double *traces = malloc((size_t)nt * nr * sizeof(double));
   double *hist = malloc((size_t)(nt - 1) * N * sizeof(double));
   if (!traces || !hist) return -1;
-  if (forward(&P, src_iz, src_ix, nr, rec_iz, rec_ix, wavelet, traces, hist)) return -1;
+  if (forward(&P, src_iz, src_ix, nr, rec_iz, rec_ix, wavelet, traces, hist, 0, NULL, NULL))
+    return -1;
   double J = 0.0;
   for (size_t e = 0; e < (size_t)nt * nr; ++e) {
     double r = traces[e] - dobs[e];

@@ -50,6 +50,9 @@ def _load():
         i, d, ll = ctypes.c_int, ctypes.c_double, ctypes.c_longlong
         L.cref_shot_forward.argtypes = [i, i, i, i, d, d, d, d, _dp, i, i, i, _ip, _ip, _dp, _dp]
         L.cref_shot_forward.restype = i
+        L.cref_shot_snapshots.argtypes = [i, i, i, i, d, d, d, d, _dp, i, i, i, _ip, _ip, _dp, i,
+                                           _ip, _dp, _dp]
+        L.cref_shot_snapshots.restype = i
         L.cref_shot_gradient.argtypes = [i, i, i, i, d, d, d, d, _dp, i, i, i, _ip, _ip, _dp, _dp,
                                          d, _dp, _dp]
         L.cref_shot_gradient.restype = i
@@ -84,6 +87,23 @@ def simulate(vel, grid: fwi.Grid, geom: fwi.Geometry, workers: int = 1):
 
     with ThreadPoolExecutor(max(1, workers)) as ex:
         list(ex.map(one, range(geom.ns)))
+    return out
+
+
+def snapshots(vel, grid: fwi.Grid, geom: fwi.Geometry, shot: int, steps):
+    """Wavefields u^n [len(steps)][NZ][NX] of shot `shot` at the ascending
+    steps `steps` (the same recurrence as oracle.fwi.forward_shot)."""
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    w = fwi.ricker(grid.nt, grid.dt, geom.f0, geom.t0)
+    rz, rx = _geom_arrays(geom)
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    out = np.zeros((len(steps), grid.NZ, grid.NX))
+    traces = np.zeros((grid.nt, geom.nr))
+    st = lib().cref_shot_snapshots(grid.nz, grid.nx, grid.nb, grid.nt, grid.dx, grid.dz, grid.dt,
+                                   grid.alpha, _p(vel), int(geom.src_iz[shot]),
+                                   int(geom.src_ix[shot]), geom.nr, _p(rz, _ip), _p(rx, _ip),
+                                   _p(w), len(steps), _p(steps, _ip), _p(out), _p(traces))
+    assert st == 0, st
     return out
 
 

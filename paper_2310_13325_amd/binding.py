@@ -485,11 +485,9 @@ def vip_grad_logpost(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor
 def vip_grad_logpost_minibatch(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,
                                dobs: torch.Tensor, sigma: float, shots: Sequence[int], **kw):
     """Unbiased minibatch estimate (section 2.4) from the shots `shots` of the
-    survey `geom` (observed data dobs [ns][nt][nr], read in place): the
-    log-likelihood and its gradient scaled by ns / len(shots), through sigma."""
-    sub = geom.subset(shots)
-    scale = len(shots) / (geom.nobs if geom.shot_index is not None else geom.ns)
-    return vip_grad_logpost(ctx, grid, sub, vel, dobs, sigma * math.sqrt(scale), **kw)
+    survey `geom` (observed data dobs [ns][nt][nr], read in place); the
+    library scales the subset's misfit by ns / len(shots) itself."""
+    return vip_grad_logpost(ctx, grid, geom.subset(shots), vel, dobs, sigma, **kw)
 
 
 def vip_grad_logpost_plain(ctx: Context, grid: Grid, geom: Geometry, vel: torch.Tensor,

@@ -16,8 +16,8 @@
 // published in a double-buffered LDS tile (two zero cells of padding on each
 // side); a thread reads its x-neighbours and the two rows beyond each end of
 // its strip from LDS and the rows inside its strip from registers.  One
-// barrier per step.  The adjoint keeps c in LDS instead and its FP32 imaging
-// sum and the prefetched aⁿ of the next step in registers.
+// barrier per step.  The adjoint keeps its imaging sum over the launch's steps
+// in FP32 registers and adds it into the FP64 accumulator once per launch.
 //
 // Points outside the padded grid have g = c = 0, so they stay exactly 0 (the
 // zero ghost layers of the scheme).  The source (forward, recompute) and the
@@ -79,11 +79,8 @@ struct BlockArgs {
   long long seg_stride;
   const float *rho;       // ADJ: residual [pair][nt][nr]
   long long rho_stride;
-  float *acc32;           // ADJ: FP32 imaging sum within a checkpoint segment [pair][N]
-  double *acc64;          // ADJ: FP64 imaging sum across segments [pair][N]
+  double *acc64;          // ADJ: FP64 imaging sum [pair][N]; each launch adds its FP32 partial
   long long acc64_stride;
-  int acc_first;          // ADJ: first launch of the segment (acc32 not read)
-  int acc_flush;          // ADJ: last launch of the segment (adds into acc64, acc32 not written)
 };
 
 constexpr int kLdsBytes = 160 * 1024;

@@ -56,10 +56,8 @@ struct StepArgs {
   long long seg_stride;
   const float *rho;       // ADJ: residual [pair][nt][nr]
   long long rho_stride;
-  float *acc32;           // ADJ: FP32 imaging sum within a segment [pair][N]
-  double *acc64;          // ADJ: FP64 imaging sum across segments [pair][N]
+  double *acc64;          // ADJ: FP64 imaging sum [pair][N]
   long long acc64_stride;
-  int acc_first, acc_flush;
 };
 
 __device__ __forceinline__ int tile_of_block(int total_tiles) {
@@ -155,21 +153,17 @@ __global__ __launch_bounds__(256) void fd_step(StepArgs a) {
       d[(long long)(a.n + 1) * a.nr + rid] = un;
       if (a.n == 0) d[rid] = 0.0f;   // u^0 = 0
     }
-    if (MODE == MODE_ADJ) {
-      float img = un * a.seg[lp * a.seg_stride + i];
-      float *acc = a.acc32 + (long long)lp * a.N;
-      if (!a.acc_first) img += acc[i];
-      if (a.acc_flush)
-        a.acc64[lp * a.acc64_stride + i] += double(img);
-      else
-        acc[i] = img;
-    }
+    if (MODE == MODE_ADJ)   // every step's product goes into the FP64 sum
+      a.acc64[lp * a.acc64_stride + i] += double(un * a.seg[lp * a.seg_stride + i]);
   }
 }
 
-// c = (v_pad dt)^2 for every particle; v_pad replicates the model edges.
+// c = (v_pad dt)^2 for every particle; v_pad replicates the model edges.  The
+// product is formed in FP64 and rounded to FP32 once: c scales the whole
+// stencil update, and each extra ulp of it shifts the simulated travel times,
+// an error that grows linearly along the sweep.
 __global__ void coeff_kernel(const float *vel, float *c, int np, int nx, int nz, int nb, int NX,
-                             int NZ, float dt, float vmax, uint32_t *status) {
+                             int NZ, double dt, float vmax, uint32_t *status) {
   long long N = (long long)NX * NZ;
   long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= N * np) return;
@@ -182,8 +176,8 @@ __global__ void coeff_kernel(const float *vel, float *c, int np, int nx, int nz,
     if (!isfinite(v)) atomicOr(status, VIP_FLAG_NONFINITE);
     else atomicOr(status, VIP_FLAG_VMAX);
   }
-  float vd = v * dt;
-  c[idx] = vd * vd;
+  const double vd = double(v) * dt;
+  c[idx] = float(vd * vd);
 }
 
 // Cerjan profile gamma(delta) = exp(-(alpha delta)^2) along one padded axis.
@@ -200,8 +194,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Residual rho = (d - dobs)/sigma^2 in place and J = 1/2 sum (d - dobs)^2/sigma^2
-// per pair (FP64, fixed reduction order).
+// Residual rho = w (d - dobs)/sigma^2 in place and J = w/2 sum (d - dobs)^2/sigma^2
+// per pair (FP64, fixed reduction order); inv_s2 = w / sigma^2, w the misfit
+// scale of a shot subset (1 for the whole survey).
 // One block of 1024 threads per pair; 16-byte accesses when the rows allow.
 constexpr int RESID_T = 1024;
 __global__ __launch_bounds__(RESID_T) void residual_kernel(float *d, long long d_stride,
@@ -443,7 +438,7 @@ vip_status launch_coeff(vip_ctx *ctx, const FwiDims &D, const vip_grid *grid, co
                         const FwiPlan &P) {
   long long total = D.N * D.np;
   coeff_kernel<<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, ctx->s()>>>(
-      vel, P.c, D.np, D.nx, D.nz, D.nb, D.NX, D.NZ, float(grid->dt), float(grid->vmax), P.status);
+      vel, P.c, D.np, D.nx, D.nz, D.nb, D.NX, D.NZ, grid->dt, float(grid->vmax), P.status);
   VIP_LAUNCH_CHECK();
   return VIP_OK;
 }
@@ -745,11 +740,8 @@ static vip_status backward_sweep_blocked(const Emitter &emit, const FwiDims &D, 
       a.rho_stride = (long long)D.nt * D.nr;
       a.seg = P.seg;
       a.seg_stride = seg_stride;
-      a.acc32 = P.acc32;
       a.acc64 = acc64;
       a.acc64_stride = N;
-      a.acc_first = n == n1 - 1;
-      a.acc_flush = n - T + 1 == n0;
       VIP_TRY(emit(BMODE_ADJ, a));
       ++launches;
       adj_zero = false;
@@ -859,11 +851,8 @@ static vip_status backward_sweep_stream(vip_ctx *ctx, const FwiDims &D, const Fw
       a.rho_stride = (long long)D.nt * D.nr;
       a.seg = P.seg + (long long)(n - n0) * N;
       a.seg_stride = seg_stride;
-      a.acc32 = P.acc32;
       a.acc64 = acc64;
       a.acc64_stride = N;
-      a.acc_first = n == n1 - 1;
-      a.acc_flush = n == n0;
       VIP_TRY(launch_step(ctx, MODE_ADJ, D.rz, npairs, a));
       z_in = a.u_out;
       Q_in = a.q_out;
@@ -893,7 +882,7 @@ vip_status launch_residual(vip_ctx *ctx, const FwiDims &D, const FwiPlan &P, int
                            int npairs, const float *dobs, double sigma) {
   long long per_pair = (long long)D.nt * D.nr;
   residual_kernel<<<dim3(npairs), dim3(RESID_T), 0, ctx->s()>>>(
-      P.resid, per_pair, dobs, P.shot_row, pair0, D.ns, per_pair, 1.0 / (sigma * sigma), P.J,
+      P.resid, per_pair, dobs, P.shot_row, pair0, D.ns, per_pair, D.misfit_scale / (sigma * sigma), P.J,
       P.status);
   VIP_LAUNCH_CHECK();
   return VIP_OK;
@@ -945,6 +934,13 @@ vip_status launch_prior_and_logpost(vip_ctx *ctx, const FwiDims &D, const FwiPla
   return VIP_OK;
 }
 
+
+// The rows of d_obs a geometry reads (and with them the misfit scale) are
+// baked into a captured graph, so they belong to its cache key.
+static void add_shot_rows(KeyBuilder &kb, const vip_geometry &g) {
+  kb.add(g.shot_index ? 1 : 0);
+  if (g.shot_index) kb.add(g.nobs).add_array(g.shot_index, g.ns);
+}
 
 // ---- batches of problems ------------------------------------------------------
 
@@ -1086,6 +1082,7 @@ vip_status vip_grad_logpost(vip_ctx *ctx, const vip_grid *grid, const vip_geomet
       .add(prior ? prior->mean : nullptr).add(prior ? prior->std : nullptr);
   kb.add_array(geom->src_ix, geom->ns).add_array(geom->src_iz, geom->ns)
       .add_array(geom->rec_ix, geom->nr).add_array(geom->rec_iz, geom->nr);
+  add_shot_rows(kb, *geom);
   return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
     VIP_TRY(upload_tables(ctx, D, grid, geom, P));
     const float *model = prior_model(ctx, D, P, vel, prior);
@@ -1204,6 +1201,7 @@ vip_status vip_grad_logpost_multi(vip_ctx *ctx, int32_t nprob, const vip_problem
         .add(q.geom.nr);
     kb.add_array(q.geom.src_ix, q.geom.ns).add_array(q.geom.src_iz, q.geom.ns)
         .add_array(q.geom.rec_ix, q.geom.nr).add_array(q.geom.rec_iz, q.geom.nr);
+    add_shot_rows(kb, q.geom);
   }
   return run_maybe_graph(ctx, kb.k, [&]() -> vip_status {
     std::vector<std::vector<std::pair<int, BlockArgs>>> fwd(nprob), bwd(nprob);

@@ -15,6 +15,11 @@ struct FwiDims {
   long long N;          // padded points per field
   int ns, nr, np;
   long long pairs;      // np * ns, pair = particle * ns + shot
+  // Rows of d_obs, and the misfit scale nobs / ns of a geometry that lists a
+  // subset of them (the unbiased minibatch estimate of section 2.4; 1 without
+  // a shot_index).
+  int nobs;
+  double misfit_scale;
   // Steps n = 0 .. nt-2 (u^n -> u^{n+1}) fall into segments: regular ones of
   // k steps over [0, n_split) and, when stored > 0, one tail segment
   // [n_split, nt-1) of the last `stored` steps.  The state at every segment
@@ -96,6 +101,8 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
   if (d.N >= (1LL << 31)) return VIP_E_UNSUPPORTED;
   d.ns = geom->ns;
   d.nr = geom->nr;
+  d.nobs = geom->shot_index ? geom->nobs : geom->ns;
+  d.misfit_scale = double(d.nobs) / double(d.ns);
   d.np = np;
   d.pairs = (long long)np * geom->ns;
   if (d.pairs >= (1LL << 31)) return VIP_E_UNSUPPORTED;
@@ -132,7 +139,8 @@ struct FwiPlan {
   float *c = nullptr;
   float *u[2] = {nullptr, nullptr}, *q[2] = {nullptr, nullptr};
   float *z[2] = {nullptr, nullptr}, *Q[2] = {nullptr, nullptr};
-  float *ckpt = nullptr, *seg = nullptr, *acc32 = nullptr;
+  float *ckpt = nullptr, *seg = nullptr;
+  float *acc32 = nullptr;   // plain path: Laplacian scratch of one field
   double *acc64 = nullptr;
   float *resid = nullptr;
   double *J = nullptr;
@@ -168,13 +176,11 @@ inline void plan_fwi(const FwiDims &D, char *base, int kind, FwiPlan *P) {
   if (kind == PLAN_GRAD) {
     P->ckpt = A.take<float>(size_t(live) * size_t(D.nseg - 1) * 2 * D.N);
     P->seg = A.take<float>(size_t(live) * size_t(D.seg_slots) * D.N);
-    P->acc32 = A.take<float>(field);
     P->resid = A.take<float>(size_t(live) * D.nt * D.nr);
     P->J = A.take<double>(D.pairs);
     P->model = A.take<float>(size_t(D.np) * D.nx * D.nz);
   } else if (kind == PLAN_TAPE) {
     P->seg = A.take<float>(size_t(live) * size_t(D.seg_slots) * D.N);
-    P->acc32 = A.take<float>(field);
   } else if (kind == PLAN_PLAIN) {
     P->hist = A.take<float>(size_t(D.nt - 1) * D.N);
     P->resid = A.take<float>(size_t(D.nt) * D.nr);

@@ -1217,13 +1217,12 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
 
 // ---- host ---------------------------------------------------------------------
 
-static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
-                              double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
-                              const vip_prior *prior, bool noise, const float *xi, uint64_t seed,
-                              uint64_t stream, double *h2_out, void *ws, size_t ws_bytes,
-                              uint32_t *status_ptr = nullptr,
-                              const vip_optimizer *opt = nullptr, int32_t kernel = VIP_KERNEL_RBF) {
-  if (!ctx || !x || !g || !ws) return VIP_E_ARG;
+// Host-side validation of one step (everything that can fail before a launch).
+static vip_status svgd_check(int32_t n, int64_t d, const float *x, const float *g, double eps,
+                             int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                             const vip_prior *prior, bool noise, const vip_optimizer *opt,
+                             int32_t kernel) {
+  if (!x || !g) return VIP_E_ARG;
   if (kernel != VIP_KERNEL_RBF && kernel != VIP_KERNEL_DIAG_VAR) return VIP_E_ARG;
   OptArgs oa;
   if (opt && noise) return VIP_E_ARG;
@@ -1232,19 +1231,40 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   if (bw_mode < VIP_BW_MEDIAN_ALL || bw_mode > VIP_BW_FIXED) return VIP_E_ARG;
   if (bw_mode == VIP_BW_FIXED && !(h_fixed > 0.0)) return VIP_E_ARG;
   if (gram_prec != VIP_GRAM_BF16 && gram_prec != VIP_GRAM_FP32) return VIP_E_ARG;
-  const float *lo = nullptr, *hi = nullptr;
   if (prior && prior->kind != VIP_PRIOR_NONE) {
     // only the clip strategy acts on the update; the transform and Gaussian
     // priors enter through the gradient
     if (prior->kind == VIP_PRIOR_UNIFORM_CLIP) {
       if (!prior->lo || !prior->hi) return VIP_E_ARG;
-      lo = prior->lo;
-      hi = prior->hi;
     } else if (prior->kind != VIP_PRIOR_UNIFORM_TRANSFORM && prior->kind != VIP_PRIOR_GAUSSIAN) {
       return VIP_E_ARG;
     }
   }
   if (noise && n > kCholMax) return VIP_E_UNSUPPORTED;
+  const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
+  if (split_update && (n + 31) / 32 * 16 > 65535) return VIP_E_UNSUPPORTED;   // a grid row per j pair
+  if (!split_update && !noise) {
+    const long long ntiles = (long long)((n + UM - 1) / UM) * ((d + UN - 1) / UN);
+    if (ntiles >= (1LL << 30)) return VIP_E_UNSUPPORTED;
+  }
+  return VIP_OK;
+}
+
+static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                              double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                              const vip_prior *prior, bool noise, const float *xi, uint64_t seed,
+                              uint64_t stream, double *h2_out, void *ws, size_t ws_bytes,
+                              uint32_t *status_ptr = nullptr,
+                              const vip_optimizer *opt = nullptr, int32_t kernel = VIP_KERNEL_RBF) {
+  if (!ctx || !ws) return VIP_E_ARG;
+  VIP_TRY(svgd_check(n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, noise, opt, kernel));
+  OptArgs oa;
+  (void)make_opt_args(opt, &oa);
+  const float *lo = nullptr, *hi = nullptr;
+  if (prior && prior->kind == VIP_PRIOR_UNIFORM_CLIP) {
+    lo = prior->lo;
+    hi = prior->hi;
+  }
   SvgdPlan P;
   plan_svgd(n, d, static_cast<char *>(ws), &P);
   if (ws_bytes < P.bytes || !aligned(ws)) return VIP_E_WORKSPACE;
@@ -1258,7 +1278,6 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
   // the BF16 path without noise never reads the FP32 Xc (it recomputes x - xbar)
   const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
-  if (split_update && (n + 31) / 32 * 16 > 65535) return VIP_E_UNSUPPORTED;   // a grid row per j pair
   // the register cache addresses X with 32-bit byte offsets, up to row 32 CACHE
   const unsigned long long rows = (unsigned long long)std::max(n, CENTRE_GROUPS * CENTRE_CACHE);
   auto *centre = rows * (unsigned long long)d * 4ull < (1ull << 31)
@@ -1329,7 +1348,6 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   } else {
     const int mblocks = (n + UM - 1) / UM;
     const long long ntiles = (long long)mblocks * ((d + UN - 1) / UN);
-    if (ntiles >= (1LL << 30)) return VIP_E_UNSUPPORTED;
     // float4 staging needs rows of a multiple of 4 floats and 16-byte aligned bases
     const int vec = (d % 4 == 0) && (n % 4 == 0) && (reinterpret_cast<uintptr_t>(g) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
@@ -1432,8 +1450,10 @@ static vip_status svgd_multi(vip_ctx *ctx, int32_t nens, const vip_ensemble *ens
                              double h_fixed, int32_t gram_prec, bool noise, uint64_t seed,
                              uint64_t stream, void *ws, size_t ws_bytes) {
   if (!ctx || !ens || !ws || nens < 1) return VIP_E_ARG;
+  // every ensemble is checked before the first is updated in place
   for (int e = 0; e < nens; ++e)
-    if (ens[e].n < 1 || ens[e].d < 1) return VIP_E_ARG;
+    VIP_TRY(svgd_check(ens[e].n, ens[e].d, ens[e].x, ens[e].g, ens[e].eps, bw_mode, h_fixed,
+                       gram_prec, &ens[e].prior, noise, nullptr, VIP_KERNEL_RBF));
   std::vector<size_t> offs;
   const size_t need = plan_svgd_multi(nens, ens, &offs);
   if (ws_bytes < need || !aligned(ws)) return VIP_E_WORKSPACE;

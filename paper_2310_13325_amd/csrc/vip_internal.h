@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -87,12 +88,16 @@ struct vip_ctx {
   bool graph_mode = false;
   int tile = -2;   // step-kernel shape: -2 automatic, -1 one step per launch, >= 0 tile table index
   std::map<std::string, hipGraphExec_t> graphs;
+  std::deque<std::string> graph_order;   // cache keys, oldest first
   // Stream the launch helpers enqueue on (user, or cap while capturing).
   hipStream_t s() const { return active; }
   hipStream_t active = nullptr;
 };
 
 namespace vip {
+
+// Graphs a context keeps; a new argument set beyond this evicts the oldest.
+constexpr size_t kMaxCachedGraphs = 32;
 
 // Runs `body` (a sequence of launches on ctx->s()) either eagerly on the user
 // stream or, in graph mode, through a cached hipGraph keyed by `key`.
@@ -119,7 +124,16 @@ vip_status run_maybe_graph(vip_ctx *ctx, const std::string &key, F &&body) {
     hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     VIP_TRY_HIP(ei);
+    if (ctx->graphs.size() >= kMaxCachedGraphs) {
+      // evict the oldest graph once its last replay has finished
+      VIP_TRY_HIP(hipStreamSynchronize(ctx->cap));
+      auto old = ctx->graphs.find(ctx->graph_order.front());
+      (void)hipGraphExecDestroy(old->second);
+      ctx->graphs.erase(old);
+      ctx->graph_order.pop_front();
+    }
     it = ctx->graphs.emplace(key, exec).first;
+    ctx->graph_order.push_back(key);
   }
   VIP_TRY_HIP(hipEventRecord(ctx->ev_in, ctx->user));
   VIP_TRY_HIP(hipStreamWaitEvent(ctx->cap, ctx->ev_in, 0));

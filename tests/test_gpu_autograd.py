@@ -69,3 +69,69 @@ def test_c3_autograd_against_adjoint_oracle_and_differences():
         worst = max(worst, abs(fd - g_auto[i, j]) / gmax)
     print(f"c3 central differences: worst |fd - g| / max|g| = {worst:.2e}", flush=True)
     assert worst <= 1e-3
+
+
+def test_autograd_forwards_before_backwards_keep_their_own_tapes():
+    """Two forwards (the second with more particles) before one backward: each
+    backward runs on its own forward's checkpoints, bit for bit the gradient
+    of that forward taken alone."""
+    from tests.cases import build_case, small_problem
+    case = build_case(small_problem("tapes", nx=50, nz=33, nt=140, ns=2, np_=4))
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    dobs = dev(case.dobs)
+    op = FwiOperator(c, grid, geom, ckpt_every=13)
+    v1 = dev(case.particles[:2]).requires_grad_(True)
+    v2 = dev(case.particles[1:4]).requires_grad_(True)
+    loss = (_misfit(fwi_forward(v1, op), dobs[None], case.sigma)
+            + 2.0 * _misfit(fwi_forward(v2, op), dobs[None], case.sigma))
+    loss.backward()
+    refs = []
+    for v, w in ((case.particles[:2], 1.0), (case.particles[1:4], 2.0)):
+        vr = dev(v).requires_grad_(True)
+        (w * _misfit(fwi_forward(vr, op), dobs[None], case.sigma)).backward()
+        refs.append(vr.grad)
+    assert torch.equal(v1.grad, refs[0]) and torch.equal(v2.grad, refs[1])
+
+
+def test_c3_autograd_all_64_particles():
+    """The differentiation workload at its stated size: 64 particles x 20 shots,
+    checkpoints every 50 steps (an 85 GB tape).  Sampled particles against the
+    FP64 oracle (gradient <= 1e-4, misfit <= 1e-5); all 64 against
+    vip_grad_logpost (the same adjoint through the library's own residual)."""
+    prob = configs.C3
+    case = build_case_c(prob)
+    assert case.particles.shape[0] == 64
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    dobs = dev(case.dobs)
+    op = FwiOperator(c, grid, geom, ckpt_every=50)
+    vel = dev(case.particles).requires_grad_(True)
+    print("c3 autograd: 64 particles forward", flush=True)
+    data = fwi_forward(vel, op)
+    J = 0.5 * ((data - dobs[None]) ** 2).sum(dim=(1, 2, 3)) / case.sigma ** 2
+    J.sum().backward()
+    J = J.detach().cpu().numpy().astype(np.float64)
+    g_auto = vel.grad.detach().cpu().numpy().astype(np.float64)
+    del data, vel
+    op._ws = None
+    torch.cuda.empty_cache()
+    print("c3 autograd: backward done", flush=True)
+
+    sampled = [0, 31, 63]
+    lp_ref, g_ref = cref.grad_logpost(case.particles[sampled], case.ogrid, case.ogeom, case.dobs,
+                                      case.sigma, workers=workers())
+    for k, p in enumerate(sampled):
+        e = rel(g_auto[p], -g_ref[k])
+        ej = abs(J[p] + lp_ref[k]) / abs(lp_ref[k])
+        print(f"c3 autograd particle {p}: grad rel L2 {e:.2e}, misfit rel {ej:.2e}", flush=True)
+        assert e <= 1e-4 and ej <= 1e-5
+
+    lp, g = vb.vip_grad_logpost(c, grid, geom, dev(case.particles), dobs, case.sigma,
+                                ckpt_every=50, live_pairs=640, ws_tag="c3all")
+    g = g.cpu().numpy()
+    c._ws.pop("c3all", None)
+    torch.cuda.empty_cache()
+    worst = max(rel(-g[p], g_auto[p]) for p in range(64))
+    print(f"c3 autograd vs vip_grad_logpost, 64 particles: worst {worst:.2e}", flush=True)
+    assert worst <= 1e-5

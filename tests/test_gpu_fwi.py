@@ -260,3 +260,94 @@ def test_grad_with_dz_unequal_dx(tile):
     assert ew <= WAVE_TOL and eg <= GRAD_TOL
     assert np.allclose(lp.cpu().numpy(), lp_ref, rtol=LOGPOST_TOL, atol=0)
     c.set_tile(-2)
+
+
+def _vertical_line_geometry(prob):
+    """Receivers on several rows, including two vertical lines (a borehole
+    array: rows 2-12 of column 40 and rows 20-29 of column 0), so that strips
+    of the step kernel hold more than one receiver per column."""
+    nx, nz = prob.nx, prob.nz
+    src = [(0, 3), (nz // 2, nx - 2), (nz - 1, nx // 2)]
+    rec = ([(r, 40) for r in range(2, 13)] + [(r, 0) for r in range(20, 30)] +
+           [(2, 5), (2, 6), (nz - 1, nx - 1), (11, 11)])
+    return ofwi.Geometry(src_iz=tuple(s[0] for s in src), src_ix=tuple(s[1] for s in src),
+                         rec_iz=tuple(r[0] for r in rec), rec_ix=tuple(r[1] for r in rec),
+                         f0=prob.f0)
+
+
+def _strips_with_two_receivers(tile, prob, og):
+    """Number of (tile, strip, column) cells of the blocked kernel holding two or
+    more receivers (checked on the host, so the test knows it exercises them)."""
+    ex, ez, rz, tmax = (vb.tile_shape(tile)[k] for k in ("ex", "ez", "rz", "tmax"))
+    h = 2 * tmax
+    iz = ez - 2 * h
+    NZ = prob.nz + 2 * prob.nb
+    rows_by_col = {}
+    for z, x in zip(og.rec_iz, og.rec_ix):
+        rows_by_col.setdefault(x + prob.nb, []).append(z + prob.nb)
+    count = 0
+    for tz in range(-(-NZ // iz)):
+        z0 = tz * iz - h
+        for strip in range(ez // rz):
+            lo = z0 + strip * rz
+            for rows in rows_by_col.values():
+                if sum(lo <= r < lo + rz for r in rows) >= 2:
+                    count += 1
+    return count
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_grad_vertical_receiver_lines(tile):
+    """Several receivers in one column within one strip (the kernel's table path
+    for further receivers, in the forward traces and in the adjoint's residual
+    injection) and residuals injected on many rows: data and gradients against
+    the oracle for every tile shape."""
+    from paper_2310_13325_amd import synth
+    prob = small_problem(nt=181, ns=3)
+    case = build_case(prob)
+    og = _vertical_line_geometry(prob)
+    if tile >= 0:
+        assert _strips_with_two_receivers(tile, prob, og) > 0
+    clean = ofwi.simulate(case.v_true, case.ogrid, og)
+    sigma = 0.01 * float(np.sqrt(np.mean(clean ** 2)))
+    r = np.random.default_rng(11)
+    dobs = f32(clean + sigma * r.standard_normal(clean.shape))
+    c = ctx()
+    c.set_tile(tile)
+    grid = vb.Grid(nx=prob.nx, nz=prob.nz, nt=prob.nt, dx=prob.dx, dt=prob.dt, vmax=case.vmax,
+                   nb=prob.nb, sponge_alpha=prob.alpha)
+    w = vb.vip_ricker(c, prob.nt, prob.dt, prob.f0)
+    geom = vb.Geometry(og.src_iz, og.src_ix, og.rec_iz, og.rec_ix, w)
+    data = vb.vip_forward(c, grid, geom, dev(case.particles)).cpu().numpy()
+    lp, g = vb.vip_grad_logpost(c, grid, geom, dev(case.particles), dev(dobs), sigma,
+                                ckpt_every=13, lo=dev(case.lo), hi=dev(case.hi), ws_tag="vline")
+    lp_ref, g_ref = ofwi.grad_logpost(case.particles, case.ogrid, og, dobs, sigma, case.lo, case.hi)
+    g = g.cpu().numpy()
+    for p in range(case.particles.shape[0]):
+        ew = rel(data[p], ofwi.simulate(case.particles[p], case.ogrid, og))
+        eg = rel(g[p], g_ref[p])
+        print(f"vertical lines, tile {tile}, particle {p}: data {ew:.2e}, grad {eg:.2e}", flush=True)
+        assert ew <= WAVE_TOL and eg <= GRAD_TOL
+    assert np.allclose(lp.cpu().numpy(), lp_ref, rtol=LOGPOST_TOL, atol=0)
+    c.set_tile(-2)
+
+
+def test_logpost_is_minus_infinity_outside_the_uniform_prior():
+    """A particle outside its uniform bounds (but below the declared velocity
+    bound) has log-posterior -inf, the others keep theirs."""
+    case = build_case(configs.C1)
+    c = ctx()
+    grid, geom = grid_geom(c, case)
+    parts = case.particles.copy()
+    row = int(np.argmin(case.hi[:, 0]))
+    assert case.hi[row, 0] + 1.0 <= case.vmax
+    parts[1, row, 7] = case.hi[row, 7] + 1.0
+    lp, g = vb.vip_grad_logpost(c, grid, geom, dev(parts), dev(case.dobs), case.sigma,
+                                ckpt_every=50, lo=dev(case.lo), hi=dev(case.hi), ws_tag="inf")
+    lp = lp.cpu().numpy()
+    lp_ref, _ = _oracle_grad(case, parts)
+    assert lp_ref[1] == -np.inf and lp[1] == -np.inf
+    others = [p for p in range(parts.shape[0]) if p != 1]
+    assert np.all(np.isfinite(lp[others]))
+    assert np.allclose(lp[others], lp_ref[others], rtol=LOGPOST_TOL, atol=0)
+    assert c.poll(c.workspace("inf", 0)) == 0

@@ -45,3 +45,19 @@ def test_sqdist_matches_numpy_oracle():
     D = cref.sqdist(X, workers=3, block=5)
     assert np.abs(D - svgd.sqdist(X)).max() <= 1e-12 * D.max()
     assert np.all(np.diag(D) == 0.0)
+
+
+def test_snapshots_match_numpy_oracle_wavefield():
+    _, grid, vel, geom = _problem(4)
+    _, c = fwi.coefficient(vel, grid)
+    g = fwi.sponge(grid)
+    w = fwi.ricker(grid.nt, grid.dt, geom.f0)
+    rec = (np.asarray(geom.rec_iz) + grid.nb, np.asarray(geom.rec_ix) + grid.nb)
+    for s in (0, 2):
+        src = (geom.src_iz[s] + grid.nb, geom.src_ix[s] + grid.nb)
+        _, _, wave = fwi.forward_shot(c, g, grid, src, rec, wavelet=w, keep_wavefield=True)
+        steps = [0, 1, 17, 64, 65, grid.nt - 1]
+        snap = cref.snapshots(vel, grid, geom, s, steps)
+        for k, n in enumerate(steps):
+            assert np.abs(snap[k] - wave[n]).max() <= 1e-12 * max(np.abs(wave[n]).max(), 1e-300), n
+        assert np.all(snap[0] == 0.0)
