@@ -51,7 +51,8 @@ typedef enum {
   VIP_E_HIP = -4,         /* HIP runtime error (launch, capture, device) */
   VIP_E_NOT_PD = -5,      /* kernel matrix not positive definite after jitter */
   VIP_E_NONFINITE = -6,   /* NaN / Inf met on the device */
-  VIP_E_UNSUPPORTED = -7  /* option not implemented */
+  VIP_E_UNSUPPORTED = -7, /* option not implemented */
+  VIP_E_SCRATCH = -8      /* larger than the fixed array of vip_svgd_step_noalloc */
 } vip_status;
 
 /* Device status bits latched in a workspace and returned by vip_poll. */
@@ -419,6 +420,25 @@ vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const fl
                           int32_t bw_mode, double h_fixed, int32_t gram_prec,
                           const vip_prior *prior, const float *xi, uint64_t seed, uint64_t stream,
                           double *h2_out, void *ws, size_t ws_bytes);
+
+/* Allocation-free SVGD step, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same step and kernels as vip_svgd_step (same arguments
+ * and results), with the workspace replaced by a fixed device array of
+ * VIP_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends.  No call allocates or frees memory.
+ *  - Size limit: VIP_E_SCRATCH when vip_svgd_workspace(n, d) exceeds
+ *    VIP_NOALLOC_SCRATCH_BYTES (e.g. n = 128 at d = 24,000 fits; n = 256 does
+ *    not); nothing is enqueued then.
+ *  - Sharing: every call on one device uses that device's single array, which
+ *    keeps the last call's contents.  Calls that may overlap on one device
+ *    (several streams, threads or contexts) race on it: serialise them.
+ *  - status: device uint32 that the step ORs its VIP_FLAG_* bits into (the
+ *    caller clears it), or NULL to drop them. */
+#define VIP_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+vip_status vip_svgd_step_noalloc(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g,
+                                 double eps, int32_t bw_mode, double h_fixed, int32_t gram_prec,
+                                 const vip_prior *prior, double *h2_out, uint32_t *status);
 
 /* Several independent ensembles, each updated as by vip_svgd_step or
  * vip_ssvgd_step (ensemble e draws its Philox normals from stream + e when its

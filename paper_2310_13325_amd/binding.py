@@ -139,6 +139,8 @@ def lib() -> ctypes.CDLL:
                                              sz]),
             "vip_ssvgd_step": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR, vp,
                                               u64, u64, vp, vp, sz]),
+            "vip_svgd_step_noalloc": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl, i32, dbl, i32, PR,
+                                                     vp, vp]),
             "vip_philox_normals": (ctypes.c_int, [vp, i64, u64, u64, vp]),
             "vip_philox_uint32": (ctypes.c_int, [vp, i64, u64, u64, vp]),
             "vip_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -580,6 +582,29 @@ def vip_svgd_step(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
                                _ptr(h2_out, torch.float64), ctypes.c_void_p(ws.data_ptr()),
                                ws.numel()), "vip_svgd_step")
     return ws
+
+
+VIP_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def vip_svgd_step_noalloc(ctx: Context, x: torch.Tensor, g: torch.Tensor, eps: float,
+                          bw_mode: int = VIP_BW_MEDIAN_ALL, h_fixed: float = 1.0,
+                          gram_prec: int = VIP_GRAM_BF16, lo=None, hi=None,
+                          h2_out: Optional[torch.Tensor] = None,
+                          status: Optional[torch.Tensor] = None,
+                          prior: Optional[Prior] = None) -> None:
+    """In-place SVGD update of x ([n][d] float32) without a workspace: the
+    library's fixed per-device array serves instead (status: device int32 [1]
+    the step ORs its flags into, or None)."""
+    ctx.sync_stream()
+    n = x.shape[0]
+    d = x.numel() // n
+    pr = _prior(lo, hi, prior)
+    _check(lib().vip_svgd_step_noalloc(ctx.handle, n, d, _ptr(x, torch.float32),
+                                       _ptr(g, torch.float32), eps, bw_mode, h_fixed, gram_prec,
+                                       ctypes.byref(pr) if pr is not None else None,
+                                       _ptr(h2_out, torch.float64), _ptr(status, torch.int32)),
+           "vip_svgd_step_noalloc")
 
 
 class Optimizer:

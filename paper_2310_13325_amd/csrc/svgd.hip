@@ -28,6 +28,7 @@
 // Distances come from centred particles: D is translation invariant, and
 // centring removes the large common velocity that BF16 could not resolve.
 #include <cmath>
+#include <mutex>
 #include <cstring>
 
 #include "vip_internal.h"
@@ -1501,3 +1502,65 @@ vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const fl
 }
 
 }  // extern "C"
+
+// ---- allocation-free variant of the SVGD step --------------------------------
+// For callers that cannot allocate device memory (code under stream capture,
+// tight serving loops, harnesses that forbid it): vip_svgd_step_noalloc runs
+// the same kernels as vip_svgd_step with the step's workspace in a fixed
+// array of the library, `scratch`, instead of a caller workspace.  In host
+// code `scratch` names a host-side stand-in, so kernels and fills are given
+// its device address, taken once per device by vip_noalloc_setup.
+
+namespace vip {
+
+static __device__ __align__(256) unsigned char scratch[VIP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kScratchDevices];
+
+// Device address of `scratch` on `device`; vip_create calls it with `device`
+// current, so every context has it before its first step.
+vip_status vip_noalloc_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return VIP_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return VIP_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_last_hip_error(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    return VIP_E_HIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return VIP_OK;
+}
+
+static void *scratch_of(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+}  // namespace vip
+
+extern "C" vip_status vip_svgd_step_noalloc(vip_ctx *ctx, int32_t n, int64_t d, float *x,
+                                            const float *g, double eps, int32_t bw_mode,
+                                            double h_fixed, int32_t gram_prec,
+                                            const vip_prior *prior, double *h2_out,
+                                            uint32_t *status) {
+  if (!ctx) return VIP_E_ARG;
+  VIP_TRY(svgd_check(n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr,
+                     VIP_KERNEL_RBF));
+  SvgdPlan P;
+  plan_svgd(n, d, nullptr, &P);
+  if (P.bytes > size_t(VIP_NOALLOC_SCRATCH_BYTES)) return VIP_E_SCRATCH;
+  void *ws = scratch_of(ctx->device);
+  if (!ws) return VIP_E_HIP;   // vip_create could not take the array's address
+  VIP_TRY_HIP(hipSetDevice(ctx->device));
+  // the array keeps the previous call's contents: the status word that the
+  // kernels latch flags into starts at zero (every other buffer the step reads
+  // is written earlier in the same step)
+  if (!status) VIP_TRY(fill_u32(ctx->user, static_cast<uint32_t *>(ws), 1, 0u));
+  return svgd_common(ctx, n, d, x, g, eps, bw_mode, h_fixed, gram_prec, prior, false, nullptr, 0,
+                     0, h2_out, ws, size_t(VIP_NOALLOC_SCRATCH_BYTES), status);
+}

@@ -137,6 +137,9 @@ const char *vip_status_string(int status) {
     case VIP_E_NOT_PD: return "VIP_E_NOT_PD: kernel matrix not positive definite";
     case VIP_E_NONFINITE: return "VIP_E_NONFINITE: non-finite value on the device";
     case VIP_E_UNSUPPORTED: return "VIP_E_UNSUPPORTED: option not implemented";
+    case VIP_E_SCRATCH:
+      return "VIP_E_SCRATCH: the step needs more than the VIP_NOALLOC_SCRATCH_BYTES (64 MiB) "
+             "fixed array of vip_svgd_step_noalloc; use vip_svgd_step with a workspace";
     default: return "unknown vip_status";
   }
 }
@@ -150,6 +153,7 @@ vip_status vip_create(vip_ctx **out, int device, void *stream) {
   VIP_TRY_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return VIP_E_ARG;
   VIP_TRY_HIP(hipSetDevice(device));
+  VIP_TRY(vip_noalloc_setup(device));
   vip_ctx *ctx = new vip_ctx();
   ctx->device = device;
   ctx->user = static_cast<hipStream_t>(stream);

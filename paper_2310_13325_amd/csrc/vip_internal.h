@@ -147,6 +147,10 @@ vip_status run_maybe_graph(vip_ctx *ctx, const std::string &key, F &&body) {
 int timing_begin(vip_ctx *ctx, int kind);
 void timing_end(vip_ctx *ctx, int run, int64_t launches, double point_steps);
 
+// Device address of the allocation-free step's fixed array on `device`
+// (svgd.hip); vip_create calls it with `device` current.
+vip_status vip_noalloc_setup(int device);
+
 // Small helpers implemented in util.hip
 vip_status fill_u32(hipStream_t s, uint32_t *p, size_t n, uint32_t v);
 vip_status fill_f32(hipStream_t s, float *p, size_t n, float v);
