@@ -414,6 +414,11 @@ vip_status vip_svgd_step_ex(vip_ctx *ctx, int32_t n, int64_t d, float *x, const 
  * noise eta = sqrt(2 eps) L xi per coordinate, L the lower Cholesky factor of
  * K/n (eq:matrixDK, eq:noise_term; factorised in FP64 on the device, with
  * jitter 1e-12 trace/n x10 per retry, at most 6 retries), then the prior clip.
+ * n <= 128 factorises in one workgroup with the matrix in LDS; larger n by
+ * right-looking 64-column panels over the whole GPU, any n.  A factorisation
+ * that needs jitter (numerically coincident particles) reruns in one
+ * workgroup with the matrix in global memory: correct, but slow for large n
+ * (VIP_FLAG_JITTER reports it).
  * xi: device float [n][d] standard normals, or NULL to draw them with
  * Philox4x32-10 (key = seed, counter = (element/4, stream)) and Box-Muller. */
 vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,

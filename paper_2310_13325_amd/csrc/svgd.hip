@@ -651,6 +651,250 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(const float *D, const do
   }
 }
 
+// ---- blocked Cholesky of K/n in FP64 for n > kCholMax --------------------------
+// Right-looking over panels of CB columns.  Per panel k0, chol_panel_kernel:
+// wave 0 of every block factors the CB x CB diagonal block with one row per
+// lane in registers (column k's entries broadcast with readlane, no barriers),
+// then inverts it (one column of L11^-1 per lane, L11 read from LDS); block 0
+// writes L11 back, the other blocks each form 64 rows of the panel below,
+// L21 = A21 L11^-T, as a small product.  chol_update_kernel then subtracts
+// L21 L21^T from the trailing lower triangle in 64 x 64 tiles.  A
+// non-positive pivot sets state[0], after which every later kernel of the
+// attempt returns at once; chol_retry_kernel then repeats the factorisation
+// with the jitter protocol of the one-workgroup kernel (delta = 1e-12
+// trace(K/n)/n, x10 per retry) in a single workgroup over the matrix in global
+// memory -- the path of (numerically) coincident particles, which trades speed
+// for simplicity.  chol_output_kernel writes L (zero above the diagonal, all
+// zero if every retry failed) and its FP32 copy.
+constexpr int CB = 32;        // panel width
+constexpr int CR = 64;        // panel rows per block below the diagonal block
+
+// A = K/n + jit I on and below the diagonal, 0 above; state[0..1] cleared.
+__global__ void chol_init_kernel(const float *D, const double *h2, double *A, int n, double jit,
+                                 uint32_t *state) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) state[0] = state[1] = 0u;
+  if (e >= (long long)n * n) return;
+  const int i = int(e / n), j = int(e - (e / n) * n);
+  double v = 0.0;
+  if (j <= i) {   // the same FP64 K/n as the one-workgroup kernel
+    v = exp(-double(D[e]) * (1.0 / (2.0 * h2[0]))) * (1.0 / double(n));
+    if (i == j) v += jit;
+  }
+  A[e] = v;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(unsigned(b), lane);
+  const unsigned hi = __builtin_amdgcn_readlane(unsigned(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__global__ __launch_bounds__(256) void chol_panel_kernel(double *A, int n, int k0,
+                                                         uint32_t *state) {
+  if (state[0]) return;
+  __shared__ double Ls[CB][CB + 1];   // L11
+  __shared__ double Li[CB][CB + 1];   // L11^-1 (lower)
+  __shared__ double As[CR][CB + 1];   // this block's rows of A21
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  const int b = min(CB, n - k0);
+  const int r0 = k0 + CB + (int(blockIdx.x) - 1) * CR;   // first A21 row (blocks >= 1)
+  if (blockIdx.x > 0)   // stage A21 while wave 0 factors
+    for (int e = t; e < CR * CB; e += 256) {
+      const int r = e / CB, k = e - (e / CB) * CB;
+      As[r][k] = r0 + r < n ? A[(long long)(r0 + r) * n + k0 + k] : 0.0;
+    }
+  if (t < 64) {
+    // lane i < CB holds row i of the diagonal block (identity beyond the
+    // matrix); lanes CB.. repeat row CB - 1 and are never read
+    const int i = t < CB ? t : CB - 1;
+    double r[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      double v = i == j ? 1.0 : 0.0;
+      if (i < b && j < b && j <= i) v = A[(long long)(k0 + i) * n + k0 + j];
+      r[j] = v;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < CB; ++k) {
+      const double p = readlane_f64(r[k], k);   // the pivot, uniform
+      ok = ok && p > 0.0;
+      const double piv = p > 0.0 ? sqrt(p) : 1.0;
+      const double l = r[k] / piv;
+      r[k] = i == k ? piv : (i > k ? l : r[k]);
+#pragma unroll
+      for (int j = k + 1; j < CB; ++j) r[j] = fma(-r[k], readlane_f64(r[k], j), r[j]);
+    }
+    if (t < CB) {
+#pragma unroll
+      for (int j = 0; j < CB; ++j) Ls[t][j] = j <= t ? r[j] : 0.0;
+    }
+    if (t == 0) bad = ok ? 0 : 1;
+    if (blockIdx.x == 0 && ok && t < b) {
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+        if (j <= t && j < b) A[(long long)(k0 + t) * n + k0 + j] = r[j];
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (blockIdx.x == 0 && t == 0) atomicOr(state, 1u);
+    return;
+  }
+  if (blockIdx.x == 0) return;
+  if (t < CB) {
+    // column j = t of L11^-1: L11 x = e_j by forward substitution
+    double x[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      double v = q == t ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < q; ++m) v = fma(-Ls[q][m], x[m], v);
+      x[q] = v / Ls[q][q];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) Li[q][t] = x[q];
+  }
+  __syncthreads();
+  // X = A21 L11^-T: thread t gives row t / 4, columns 8 (t % 4) .. + 7
+  const int rr = t >> 2, c0 = (t & 3) * 8;
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll 8
+  for (int m = 0; m < CB; ++m) {
+    const double a = As[rr][m];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = fma(a, Li[c0 + c][m], acc[c]);
+  }
+  if (r0 + rr < n) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) A[(long long)(r0 + rr) * n + k0 + c0 + c] = acc[c];
+  }
+}
+
+// Trailing update A22 -= L21 L21^T on the lower triangle, 64 x 64 tiles (tile
+// (ti, tj) with tj <= ti), 256 threads with 4 x 4 outputs each.
+__global__ __launch_bounds__(256) void chol_update_kernel(double *A, int n, int k0,
+                                                          uint32_t *state) {
+  if (state[0]) return;
+  __shared__ double Li[64][CB + 1], Lj[64][CB + 1];
+  const int r0 = k0 + CB;
+  const int b = CB;   // update panels are always full: a short last panel has no trailing part
+  // lower-triangle tile of this block: tb = ti (ti + 1) / 2 + tj
+  const int tb = blockIdx.x;
+  int ti = int((sqrt(8.0 * tb + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= tb) ++ti;
+  while (ti * (ti + 1) / 2 > tb) --ti;
+  const int tj = tb - ti * (ti + 1) / 2;
+  const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
+  const int t = threadIdx.x;
+  for (int e = t; e < 64 * CB; e += 256) {
+    const int r = e / CB, k = e - (e / CB) * CB;
+    Li[r][k] = i0 + r < n ? A[(long long)(i0 + r) * n + k0 + k] : 0.0;
+    Lj[r][k] = j0 + r < n ? A[(long long)(j0 + r) * n + k0 + k] : 0.0;
+  }
+  __syncthreads();
+  const int ty = t >> 4, tx = t & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < b; ++k) {
+    double a[4], bb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] = Li[ty + 16 * r][k];
+      bb[r] = Lj[tx + 16 * r][k];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], bb[c], acc[r][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + ty + 16 * r;
+    if (i >= n) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + tx + 16 * c;
+      if (j <= i && j < n) A[(long long)i * n + j] -= acc[r][c];
+    }
+  }
+}
+
+// After a failed blocked attempt: the jitter retries in one workgroup over the
+// matrix in global memory (right-looking, column by column).  state[1] = 1
+// when every retry failed.
+__global__ __launch_bounds__(1024) void chol_retry_kernel(const float *D, const double *h2,
+                                                          double *A, int n, int max_retries,
+                                                          uint32_t *state, uint32_t *status) {
+  __shared__ int fail;
+  if (!state[0]) return;   // the blocked attempt succeeded
+  const int t = threadIdx.x, nt = blockDim.x;
+  const double inv2h2 = 1.0 / (2.0 * h2[0]);
+  const double invn = 1.0 / double(n);
+  double delta = 1e-12 * (double(n) * invn) / double(n);   // trace(K/n)/n with K_ii = 1
+  bool ok = false;
+  int attempt = 1;
+  for (; attempt <= max_retries; ++attempt) {
+    for (long long e = t; e < (long long)n * n; e += nt) {
+      const int i = int(e / n), j = int(e - (e / n) * n);
+      double v = 0.0;
+      if (j <= i) v = exp(-double(D[e]) * inv2h2) * invn + (i == j ? delta : 0.0);
+      A[e] = v;
+    }
+    if (t == 0) fail = 0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      if (t == 0) {
+        const double p = A[(long long)k * n + k];
+        if (!(p > 0.0)) fail = 1;
+        A[(long long)k * n + k] = p > 0.0 ? sqrt(p) : 1.0;
+      }
+      __syncthreads();
+      if (fail) break;
+      const double piv = A[(long long)k * n + k];
+      for (int i = k + 1 + t; i < n; i += nt) A[(long long)i * n + k] /= piv;
+      __syncthreads();
+      const long long m = n - k - 1;
+      for (long long e = t; e < m * m; e += nt) {
+        const int i = k + 1 + int(e / m), j = k + 1 + int(e % m);
+        if (j <= i) A[(long long)i * n + j] -= A[(long long)i * n + k] * A[(long long)j * n + k];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!fail) {
+      ok = true;
+      break;
+    }
+    delta *= 10.0;
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (ok) atomicOr(status, VIP_FLAG_JITTER);
+    else atomicOr(status, VIP_FLAG_NOT_PD);
+    state[1] = ok ? 0u : 1u;
+  }
+}
+
+// L = the factor (lower part; all zero after a failure) in FP64 and FP32.
+__global__ void chol_output_kernel(double *A, float *Lf, int n, const uint32_t *state) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = int(e / n), j = int(e - (e / n) * n);
+  const double v = (j <= i && !state[1]) ? A[e] : 0.0;
+  A[e] = v;
+  Lf[e] = float(v);
+}
+
 __global__ void philox_fill_kernel(float *out, long long count, uint32_t k0, uint32_t k1,
                                    uint32_t s0, uint32_t s1) {
   long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1241,7 +1485,6 @@ static vip_status svgd_check(int32_t n, int64_t d, const float *x, const float *
       return VIP_E_ARG;
     }
   }
-  if (noise && n > kCholMax) return VIP_E_UNSUPPORTED;
   const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
   if (split_update && (n + 31) / 32 * 16 > 65535) return VIP_E_UNSUPPORTED;   // a grid row per j pair
   if (!split_update && !noise) {
@@ -1332,8 +1575,30 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
 
   dim3 ugrid(unsigned((d + 63) / 64), unsigned((n + 63) / 64));
   if (noise) {
-    cholesky_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, P.Lf, n, 6, P.status);
-    VIP_LAUNCH_CHECK();
+    if (n <= kCholMax) {
+      cholesky_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, P.Lf, n, 6, P.status);
+      VIP_LAUNCH_CHECK();
+    } else {
+      const unsigned nn_blocks = unsigned((nn + 255) / 256);
+      chol_init_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.D, P.h2, P.L, n, 0.0, P.chol);
+      VIP_LAUNCH_CHECK();
+      for (int k0 = 0; k0 < n; k0 += CB) {
+        const int below = std::max(0, n - k0 - CB);
+        chol_panel_kernel<<<dim3(unsigned(1 + (below + CR - 1) / CR)), dim3(256), 0, s>>>(
+            P.L, n, k0, P.chol);
+        VIP_LAUNCH_CHECK();
+        if (below > 0) {
+          const int m = (below + 63) / 64;
+          chol_update_kernel<<<dim3(unsigned(m * (m + 1) / 2)), dim3(256), 0, s>>>(P.L, n, k0,
+                                                                                  P.chol);
+          VIP_LAUNCH_CHECK();
+        }
+      }
+      chol_retry_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, n, 6, P.chol, P.status);
+      VIP_LAUNCH_CHECK();
+      chol_output_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.L, P.Lf, n, P.chol);
+      VIP_LAUNCH_CHECK();
+    }
     const float *xin = xi;
     if (!xin) {
       long long count_xi = (long long)n * d;

@@ -15,6 +15,7 @@ struct SvgdPlan {
   uint16_t *xc16 = nullptr;
   float *part = nullptr, *D = nullptr, *K = nullptr, *s = nullptr;
   uint32_t *hist = nullptr, *sel = nullptr;
+  uint32_t *chol = nullptr;   // blocked Cholesky: [0] attempt failed, [1] every retry failed
   double *h2 = nullptr, *L = nullptr;
   float *Lf = nullptr, *xi = nullptr, *phi = nullptr;
   uint16_t *khi = nullptr, *klo = nullptr;   // K split into BF16 pairs, rows of ldk
@@ -73,6 +74,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->s = A.take<float>(size_t(n));
   P->hist = A.take<uint32_t>(512);
   P->sel = A.take<uint32_t>(8);
+  P->chol = A.take<uint32_t>(2);
   P->h2 = A.take<double>(1);
   P->L = A.take<double>(nn);
   P->Lf = A.take<float>(nn);

@@ -327,3 +327,63 @@ def test_diag_matrix_kernel_ssvgd_matches_oracle():
     e = rel(x.cpu().numpy() - X, Xr - X)
     print(f"diag kernel sSVGD: displacement rel L2 {e:.2e}", flush=True)
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("n", [129, 600, 1000, 2048])
+def test_ssvgd_blocked_cholesky_matches_oracle(n):
+    """sSVGD beyond one workgroup's LDS (n > 128): the blocked FP64 Cholesky of
+    K/n (64-column panels) and the noise L Xi with the same normals on both
+    sides, d = 4096, FP32 Gram: L <= 1e-5, x' <= 1e-6, displacement <= 1e-3.
+    The displacement (about 0.5 per coordinate here) is bounded by the FP32
+    storage of x' itself: half an ulp at x ~ 3000 is 1.2e-4, so its relative
+    error cannot go much below 1e-4 whatever the arithmetic."""
+    from oracle import cref
+    from tests.cases import workers
+    d, eps = 4096, 20.0
+    X, G = _ensemble(n, d, 40 + n)
+    xi = np.random.default_rng(41 + n).standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    print(f"blocked cholesky n={n}", flush=True)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), eps, xi=dev(xi), gram_prec=vb.VIP_GRAM_FP32,
+                           ws_tag=f"chol{n}")
+    flags = c.poll(ws)
+    D, K, h2, phi, L = _inspect(ws, n, d)
+    info = osvgd.svgd_direction(X, G, D=cref.sqdist(X, workers=workers()))
+    eta, L_ref, retries = osvgd.ssvgd_noise(info["K"], eps, xi)
+    Xr = X + eps * info["phi"] + eta
+    xn = x.cpu().numpy().astype(np.float64)
+    eL, eX, edX = rel(L, L_ref), rel(xn, Xr), rel(xn - X, Xr - X)
+    print(f"  L {eL:.2e}, x' {eX:.2e}, displacement {edX:.2e}, oracle retries {retries}",
+          flush=True)
+    assert flags == 0 and retries == 0
+    assert eL <= 1e-5 and eX <= 1e-6 and edX <= 1e-3
+    assert np.array_equal(L, np.tril(L)) and np.all(np.diag(L) > 0)
+    c._ws.pop(f"chol{n}", None)
+
+
+@pytest.mark.parametrize("n, ndup", [(200, 200), (300, 10)])
+def test_ssvgd_blocked_cholesky_coincident_particles(n, ndup):
+    """Coincident particles make K/n singular: the blocked factorisation fails,
+    the jitter retries succeed (flag VIP_FLAG_JITTER), L L^T reproduces the
+    jittered K/n, and the update matches the oracle's (which also retries)."""
+    d, eps = 512, 5.0
+    X, G = _ensemble(n, d, 60 + n)
+    X[1:ndup] = X[0]
+    G[1:ndup] = G[0]
+    xi = np.random.default_rng(61 + n).standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), eps, xi=dev(xi), gram_prec=vb.VIP_GRAM_FP32,
+                           ws_tag="chol_dup")
+    flags = c.poll(ws)
+    D, K, h2, phi, L = _inspect(ws, n, d)
+    Xr, info = osvgd.ssvgd_step(X, G, eps, xi)
+    A = np.exp(-D.astype(np.float64) / (2.0 * h2)) / n
+    e = rel(x.cpu().numpy(), Xr)
+    print(f"coincident n={n} dup={ndup}: flags {flags}, oracle retries {info['retries']}, "
+          f"|LL^T - K/n| {np.abs(L @ L.T - A).max():.2e}, x' {e:.2e}", flush=True)
+    assert info["retries"] >= 1 and flags == vb.VIP_FLAG_JITTER
+    assert np.abs(L @ L.T - A).max() <= 1e-6 * A.max()
+    assert e <= 1e-5
+    c._ws.pop("chol_dup", None)
