@@ -672,6 +672,22 @@ def main():
             diag()
         torch.cuda.synchronize()
         svgd["bf16_gram_diag_kernel"] = round(reps / (time.perf_counter() - t), 2)
+        # sSVGD at the paper's FWI ensemble size (600) and at n = 2048: the
+        # noise needs the FP64 Cholesky of K/n, blocked over the GPU beyond 128
+        for nn in (600, 2048):
+            Xs, Gs = Xc[:nn].clone(), Gc[:nn].contiguous()
+            call = lambda k: vb.vip_ssvgd_step(ctx, Xs, Gs, case.eps, seed=5, stream=k,
+                                               gram_prec=vb.VIP_GRAM_BF16, ws_tag="c5s")
+            for k in range(2):
+                call(k)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for k in range(10):
+                call(2 + k)
+            torch.cuda.synchronize()
+            svgd[f"ssvgd_bf16_gram_n{nn}"] = round(10 / (time.perf_counter() - t), 2)
+            del Xs, Gs
+        ctx._ws.pop("c5s", None)
         # matrix-core work of one BF16-path step: the Gram's 136 upper 128 x 128
         # blocks of 256 (2 n^2 d x 136/256) and the split update's three
         # products (3 x 2 n^2 d), against the dense BF16 peak

@@ -153,8 +153,10 @@ __global__ __launch_bounds__(256) void fd_step(StepArgs a) {
       d[(long long)(a.n + 1) * a.nr + rid] = un;
       if (a.n == 0) d[rid] = 0.0f;   // u^0 = 0
     }
-    if (MODE == MODE_ADJ)   // every step's product goes into the FP64 sum
-      a.acc64[lp * a.acc64_stride + i] += double(un * a.seg[lp * a.seg_stride + i]);
+    if (MODE == MODE_ADJ)   // every step's product goes into the FP64 sum (one add per point)
+      __hip_atomic_fetch_add(a.acc64 + lp * a.acc64_stride + i,
+                             double(un * a.seg[lp * a.seg_stride + i]), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -456,6 +458,7 @@ static const TileCfg kTiles[] = {
     {96, 96, 12, 4},     // 2: interior 80 x 80, 768 threads
     {64, 64, 8, 4},      // 3: interior 48 x 48, 512 threads
     {128, 64, 8, 4},     // 4: interior 112 x 48, 1024 threads
+    {104, 104, 13, 6},   // 5: interior 80 x 80, 832 threads
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -534,6 +537,7 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
   VIP_BLOCK_CASE(2, 96, 96, 12, 4)
   VIP_BLOCK_CASE(3, 64, 64, 8, 4)
   VIP_BLOCK_CASE(4, 128, 64, 8, 4)
+  VIP_BLOCK_CASE(5, 104, 104, 13, 6)
 #undef VIP_BLOCK_CASE
 #undef VIP_BLOCK_MODES
   return VIP_E_UNSUPPORTED;
@@ -567,6 +571,7 @@ static vip_status launch_multi(vip_ctx *ctx, int cfg,
   VIP_MULTI_CASE(2, 96, 96, 12, 4)
   VIP_MULTI_CASE(3, 64, 64, 8, 4)
   VIP_MULTI_CASE(4, 128, 64, 8, 4)
+  VIP_MULTI_CASE(5, 104, 104, 13, 6)
 #undef VIP_MULTI_CASE
   return VIP_E_UNSUPPORTED;
 }
