@@ -286,10 +286,11 @@ def c1_rate(ctx, vb, synth, torch, configs):
             "particle_gradients_per_s": round(steps * n / sec, 1), "tile": ctx.tile_for(S1["grid"])}
 
 
-def c3_rate(ctx, vb, synth, torch, configs, autotune):
+def c3_rate(ctx, vb, synth, torch, configs, autotune, fixed=None):
     """c3: 64 particles x 20 shots on 400 x 200 cells at 12.5 m, nt = 4000:
     particle-gradients/s with the tile and memory schedule (checkpoint
-    interval 50, stored tail steps, live pairs) picked by the autotuner."""
+    interval 50, stored tail steps, live pairs) picked by the autotuner, or
+    `fixed` = (tile, stored_steps, live_pairs)."""
     prob = configs.C3
     S3 = setup(prob, ctx, vb, synth, torch, prob.np)
     n = prob.np
@@ -300,9 +301,14 @@ def c3_rate(ctx, vb, synth, torch, configs, autotune):
         lo=S3["lo"], hi=S3["hi"], logpost=lp, grad=g, stored_steps=st, live_pairs=live,
         ws_tag="c3")
     torch.cuda.empty_cache()
-    budget = int(torch.cuda.mem_get_info()[0] + ctx.workspace_bytes() - 8e9)
-    cands = autotune.schedules(S3["grid"], S3["geom"], n, prob.ckpt_every, budget)
-    tile, st, live, tm = autotune.tune_joint(ctx, fn, cands, tiles=[0, 2])
+    if fixed is None:
+        budget = int(torch.cuda.mem_get_info()[0] + ctx.workspace_bytes() - 8e9)
+        cands = autotune.schedules(S3["grid"], S3["geom"], n, prob.ckpt_every, budget)
+        tile, st, live, tm = autotune.tune_joint(ctx, fn, cands, tiles=[0, 2])
+    else:
+        tile, st, live = fixed
+        cands = [(st, live)]
+        ctx.set_tile(tile)
     ctx.read_timing()
     ctx.set_timing(True)
     sec = _timed(torch, lambda: fn(st, live), 2)
@@ -407,6 +413,10 @@ def main():
     ap.add_argument("--no-advi", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the c1, c3 and c4 workload rates")
+    ap.add_argument("--workloads", default="c1,c4,c3",
+                    help="which of the c1, c3, c4 workload rates to run (comma list)")
+    ap.add_argument("--c3-schedule", default=None, metavar="TILE,STORED,LIVE",
+                    help="fixed c3 tile and memory schedule (no tuning)")
     ap.add_argument("--graph", action="store_true", help="replay the gradient through a hipGraph")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile shape (no tile tuning)")
     ap.add_argument("--stored-steps", type=int, default=None,
@@ -616,14 +626,20 @@ def main():
         ctx._ws.pop("grad", None)
         torch.cuda.empty_cache()
         work = {}
-        work["c1"] = c1_rate(ctx, vb, synth, torch, configs)
-        log(f"c1: {work['c1']}")
-        work["c4"] = c4_rates(ctx, vb, synth, torch, configs, autotune)
-        log(f"c4: {work['c4']}")
-        work["c3"], S3 = c3_rate(ctx, vb, synth, torch, configs, autotune)
-        sched3 = {"tile": work["c3"]["tile"], "stored_steps": work["c3"]["stored_steps"],
-                  "live_pairs": work["c3"]["live_pairs"]}
-        log(f"c3: {work['c3']}")
+        which = [w.strip() for w in args.workloads.split(",") if w.strip()]
+        if "c1" in which:
+            work["c1"] = c1_rate(ctx, vb, synth, torch, configs)
+            log(f"c1: {work['c1']}")
+        if "c4" in which:
+            work["c4"] = c4_rates(ctx, vb, synth, torch, configs, autotune)
+            log(f"c4: {work['c4']}")
+        if "c3" in which:
+            fixed = (None if args.c3_schedule is None
+                     else tuple(int(v) for v in args.c3_schedule.split(",")))
+            work["c3"], S3 = c3_rate(ctx, vb, synth, torch, configs, autotune, fixed)
+            sched3 = {"tile": work["c3"]["tile"], "stored_steps": work["c3"]["stored_steps"],
+                      "live_pairs": work["c3"]["live_pairs"]}
+            log(f"c3: {work['c3']}")
         extra["workloads"] = work
         ctx.set_tile(main_tile)
     if not args.no_plain:
