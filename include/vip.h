@@ -418,7 +418,9 @@ vip_status vip_svgd_step_ex(vip_ctx *ctx, int32_t n, int64_t d, float *x, const 
  * right-looking 64-column panels over the whole GPU, any n.  A factorisation
  * that needs jitter (numerically coincident particles) reruns in one
  * workgroup with the matrix in global memory: correct, but slow for large n
- * (VIP_FLAG_JITTER reports it).
+ * (VIP_FLAG_JITTER reports it).  The direction phi is formed as in
+ * vip_svgd_step (with the same Gram precision); the noise product L xi runs on
+ * the FP32 matrix cores over the lower triangle of L, and the clip follows it.
  * xi: device float [n][d] standard normals, or NULL to draw them with
  * Philox4x32-10 (key = seed, counter = (element/4, stream)) and Box-Muller. */
 vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,

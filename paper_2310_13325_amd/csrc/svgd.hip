@@ -597,7 +597,7 @@ __global__ __launch_bounds__(256) void rbf_kernel(const float *D, const double *
 constexpr int kCholMax = 128;
 
 __global__ __launch_bounds__(1024) void cholesky_kernel(const float *D, const double *h2, double *L,
-                                                        float *Lf, int n, int max_retries,
+                                                        float *LfT, int n, int max_retries,
                                                         uint32_t *status) {
   __shared__ double A[kCholMax][kCholMax + 1];
   __shared__ int fail;
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(const float *D, const do
     int i = e / n, j = e - (e / n) * n;
     double v = (ok && j <= i) ? A[i][j] : 0.0;
     L[e] = v;
-    Lf[e] = float(v);
+    LfT[(long long)j * n + i] = float(v);
   }
 }
 
@@ -885,14 +885,18 @@ __global__ __launch_bounds__(1024) void chol_retry_kernel(const float *D, const 
   }
 }
 
-// L = the factor (lower part; all zero after a failure) in FP64 and FP32.
-__global__ void chol_output_kernel(double *A, float *Lf, int n, const uint32_t *state) {
+// L = the factor (lower part; all zero after a failure) in FP64, and its FP32
+// copy transposed (LfT[j][i] = L[i][j], the layout the noise product stages).
+// Each element of A is read and rewritten by the thread that writes its
+// transposed copy.
+__global__ void chol_output_kernel(double *A, float *LfT, int n, const uint32_t *state) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)n * n) return;
-  const int i = int(e / n), j = int(e - (e / n) * n);
-  const double v = (j <= i && !state[1]) ? A[e] : 0.0;
-  A[e] = v;
-  Lf[e] = float(v);
+  const int j = int(e / n), i = int(e - (e / n) * n);   // e = j n + i
+  double *a = A + (long long)i * n + j;
+  const double v = (j <= i && !state[1]) ? *a : 0.0;
+  *a = v;
+  LfT[e] = float(v);
 }
 
 __global__ void philox_fill_kernel(float *out, long long count, uint32_t k0, uint32_t k1,
@@ -903,109 +907,6 @@ __global__ void philox_fill_kernel(float *out, long long count, uint32_t k0, uin
   philox_normals4(uint64_t(q), k0, k1, s0, s1, z);
   for (int k = 0; k < 4; ++k)
     if (4 * q + k < count) out[4 * q + k] = z[k];
-}
-
-// ---- fused update GEMM --------------------------------------------------------
-// Tile 64 particles x 64 coordinates, 256 threads with 4x4 outputs each,
-// j staged 16 at a time.  Accumulates KG = K G, KX = K Xc and, with NOISE,
-// LX = L Xi; the epilogue forms phi, writes it, and updates x in place (x is
-// read only at the element this thread writes).
-// phi_i = 1/n [ sum_j K_ij (g_j - xc_j / h^2) + s_i xc_i / h^2 ]: the two
-// products K G and K Xc of eq:phi_mean regrouped into one, B = G - Xc / h^2
-// formed while staging tiles (its FP32 rounding bound, eps s_i (|g| + |xc| / h^2),
-// is the one the two separate products have).
-template <bool NOISE>
-__global__ __launch_bounds__(256) void update_kernel(const float *K, const float *Lf,
-                                                     const float *g, const float *xc,
-                                                     const float *vq, const float *xi,
-                                                     const float *s,
-                                                     const double *h2, float *x, float *phi,
-                                                     const float *lo, const float *hi, int n,
-                                                     long long d, float eps, float noise_scale,
-                                                     uint32_t *status) {
-  constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ float Ak[BK][BM + 4];
-  __shared__ float Al[NOISE ? BK : 1][BM + 4];
-  __shared__ float Bb[BK][BN + 4];
-  __shared__ float Bz[NOISE ? BK : 1][BN + 4];
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  const long long a0 = (long long)blockIdx.x * BN;
-  const int i0 = blockIdx.y * BM;
-  const float inv_h2 = float(1.0 / h2[0]);
-  float kb[4][4], lz[4][4];
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) kb[r][c] = lz[r][c] = 0.0f;
-  for (int j0 = 0; j0 < n; j0 += BK) {
-    for (int it = 0; it < 4; ++it) {
-      int idx = t + it * 256;             // 64 rows x 16 j
-      int ii = idx >> 4, jj = idx & 15;
-      bool ok = (i0 + ii < n) && (j0 + jj < n);
-      Ak[jj][ii] = ok ? K[(long long)(i0 + ii) * n + j0 + jj] : 0.0f;
-      if (NOISE) Al[jj][ii] = ok ? Lf[(long long)(i0 + ii) * n + j0 + jj] : 0.0f;
-      int jr = idx >> 6, ac = idx & 63;   // 16 j x 64 coordinates
-      bool okb = (j0 + jr < n) && (a0 + ac < d);
-      long long src = (long long)(j0 + jr) * d + a0 + ac;
-      Bb[jr][ac] = okb ? fmaf(-xc[src], inv_h2, vq ? g[src] * vq[a0 + ac] : g[src]) : 0.0f;
-      if (NOISE) Bz[jr][ac] = okb ? xi[src] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < BK; ++jj) {
-      float av[4], bb[4], al[4], bz[4];
-      for (int e = 0; e < 4; ++e) {
-        av[e] = Ak[jj][ty * 4 + e];
-        bb[e] = Bb[jj][tx * 4 + e];
-        if (NOISE) {
-          al[e] = Al[jj][ty * 4 + e];
-          bz[e] = Bz[jj][tx * 4 + e];
-        }
-      }
-      for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) {
-          kb[r][c] = fmaf(av[r], bb[c], kb[r][c]);
-          if (NOISE) lz[r][c] = fmaf(al[r], bz[c], lz[r][c]);
-        }
-    }
-    __syncthreads();
-  }
-  const float inv_n = 1.0f / float(n);
-  bool bad = false;
-  // All loads first, then the arithmetic and stores (the stores could alias
-  // the loads as far as the compiler knows, which would serialise them); the
-  // loads are unconditional (elements outside the ensemble read element 0 and
-  // are never used), so no branch separates them.
-  float xv[4][4], cv[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + ty * 4 + r;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const long long a = a0 + tx * 4 + c;
-      const long long e = (i < n && a < d) ? (long long)i * d + a : 0;
-      xv[r][c] = x[e];
-      cv[r][c] = xc[e];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + ty * 4 + r;
-    if (i >= n) break;
-    const float si = s[i] * inv_h2;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const long long a = a0 + tx * 4 + c;
-      if (a >= d) break;
-      const long long e = (long long)i * d + a;
-      const float p = fmaf(si, cv[r][c], kb[r][c]) * inv_n;
-      phi[e] = p;
-      float v = xv[r][c] + eps * p;
-      if (NOISE) v += (vq ? noise_scale * sqrtf(vq[a]) : noise_scale) * lz[r][c];
-      if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
-      bad |= !isfinite(v);
-      x[e] = v;
-    }
-  }
-  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
 // The same update (without noise) with the product on the FP32 matrix cores
@@ -1178,6 +1079,118 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
         }
       }
   }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+}
+
+// The sSVGD noise on the FP32 matrix cores, after the update has added eps phi
+// (without the clip): x <- clip(x + sqrt(2 eps) sqrt(vq) (L Xi)) per element,
+// vq = 1 / q of the diagonal matrix kernel (or 1).  Same blocks, staging and
+// layouts as update_mfma_kernel, with A = L and B = Xi: the A tile
+// As[k][i] = L[i0 + i][j0 + k] is a row segment of the transposed FP32 copy
+// LfT, and since L is lower triangular a block of rows i0 .. i0 + UM - 1 takes
+// j < i0 + UM only (about half the product overall).
+__global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const float *xi,
+                                                        const float *vq, float *x,
+                                                        const float *lo, const float *hi, int n,
+                                                        long long d, int mblocks, int vec,
+                                                        float scale, uint32_t *status) {
+  __shared__ __attribute__((aligned(16))) float As[UK][UM + UP];   // As[k][i] = L[i0 + i][j0 + k]
+  __shared__ __attribute__((aligned(16))) float Bs[UK][UN + UP];   // Bs[k][a] = Xi[j0 + k][a0 + a]
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  const int nt = mblocks * int((d + UN - 1) / UN);
+  if (tb >= nt) return;
+  const int i0 = (tb % mblocks) * UM;
+  const long long a0 = (long long)(tb / mblocks) * UN;
+  const int jend = min(n, i0 + UM);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const int ak = t >> 6, ac = (t & 63) * 4;
+  const int bk = t >> 5, bc = (t & 31) * 4;
+  float4 pa[2], pb;
+  auto load4 = [&](const float *base, long long off, long long lim) {
+    if (vec && off + 3 < lim) return *reinterpret_cast<const float4 *>(base + off);
+    float tmp[4];
+    for (int q = 0; q < 4; ++q) tmp[q] = (off + q < lim) ? base[off + q] : 0.f;
+    return make_float4(tmp[0], tmp[1], tmp[2], tmp[3]);
+  };
+  auto load_stage = [&](int j0) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int j = j0 + ak + 8 * e;
+      pa[e] = j < jend ? load4(LfT + (long long)j * n, i0 + ac, n) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int j = j0 + bk;
+    pb = j < jend ? load4(xi + (long long)j * d, a0 + bc, d) : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) *reinterpret_cast<float4 *>(&As[ak + 8 * e][ac]) = pa[e];
+    *reinterpret_cast<float4 *>(&Bs[bk][bc]) = pb;
+  };
+  f32x16_t acc[2][2];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 2; ++q)
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  load_stage(0);
+  for (int j0 = 0; j0 < jend; j0 += UK) {
+    __syncthreads();
+    store_stage();
+    __syncthreads();
+    if (j0 + UK < jend) load_stage(j0 + UK);
+#pragma unroll
+    for (int kk = 0; kk < UK; kk += 2) {
+      const int k = kk + (lane >> 5);
+      float fa[2], fb[2];
+      for (int m = 0; m < 2; ++m) fa[m] = As[k][wi * 64 + m * 32 + (lane & 31)];
+      for (int q = 0; q < 2; ++q) fb[q] = Bs[k][wj * 64 + q * 32 + (lane & 31)];
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m], fb[q], acc[m][q], 0, 0, 0);
+    }
+  }
+  // epilogue in batches of four result registers, loads before stores
+  const int lrow = wi * 64 + 4 * (lane >> 5);
+  const int lcol = wj * 64 + (lane & 31);
+  const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
+  float sc[2], lov[2], hiv[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const long long a = a0 + lcol + q * 32;
+    sc[q] = (vq && a < d) ? scale * sqrtf(vq[a]) : scale;
+    lov[q] = (lo && a < d) ? lo[a] : 0.0f;
+    hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
+  }
+  bool bad = false;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int rb = 0; rb < 16; rb += 4) {
+      float xv[4][2];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
+        const int i = i0 + lrow + lr;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const bool in = i < n && a0 + lcol + q * 32 < d;
+          xv[rr][q] = x[in ? el + (long long)lr * d + q * 32 : 0];
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
+        if (i0 + lrow + lr >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (a0 + lcol + q * 32 >= d) continue;
+          float v = fmaf(sc[q], acc[m][q][r], xv[rr][q]);
+          if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
+          bad |= !isfinite(v);
+          x[el + (long long)lr * d + q * 32] = v;
+        }
+      }
+    }
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
@@ -1485,9 +1498,9 @@ static vip_status svgd_check(int32_t n, int64_t d, const float *x, const float *
       return VIP_E_ARG;
     }
   }
-  const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
+  const bool split_update = gram_prec == VIP_GRAM_BF16;
   if (split_update && (n + 31) / 32 * 16 > 65535) return VIP_E_UNSUPPORTED;   // a grid row per j pair
-  if (!split_update && !noise) {
+  {
     const long long ntiles = (long long)((n + UM - 1) / UM) * ((d + UN - 1) / UN);
     if (ntiles >= (1LL << 30)) return VIP_E_UNSUPPORTED;
   }
@@ -1573,7 +1586,35 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                                            split_update ? P.khi : nullptr, P.klo, P.ldk);
   VIP_LAUNCH_CHECK();
 
-  dim3 ugrid(unsigned((d + 63) / 64), unsigned((n + 63) / 64));
+  // phi and x + eps phi (or a step rule); with noise the prior clip waits for
+  // the noise pass, which adds the noise to the updated x and then clips
+  const float *ulo = noise ? nullptr : lo, *uhi = noise ? nullptr : hi;
+  const int mblocks = (n + UM - 1) / UM;
+  const long long ntiles = (long long)mblocks * ((d + UN - 1) / UN);
+  // float4 staging needs rows of a multiple of 4 floats and 16-byte aligned bases
+  const int vec = (d % 4 == 0) && (n % 4 == 0) && (reinterpret_cast<uintptr_t>(g) % 16 == 0) &&
+                  (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
+                  (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
+  if (split_update) {
+    const int npairs = P.ldk / 2;
+    const int bvec = d % 4 == 0 && reinterpret_cast<uintptr_t>(g) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(x) % 16 == 0;
+    bpair_kernel<<<dim3(unsigned((P.dp + 1023) / 1024), unsigned(npairs)), dim3(256), 0, s>>>(
+        g, x, P.xbar, vq, P.h2, P.bph, P.bpl, n, d, P.dp, bvec);
+    VIP_LAUNCH_CHECK();
+    const int vblocks = (n + VM - 1) / VM;
+    const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
+    auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x3_kernel<false> : update_bf16x3_kernel<true>;
+    kern<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
+        P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, ulo, uhi, n, d,
+        vblocks, float(eps), oa, P.status);
+  } else {
+    auto *kern = oa.kind == VIP_OPT_SGD ? update_mfma_kernel<false> : update_mfma_kernel<true>;
+    kern<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
+        P.K, g, P.xc, vq, P.s, P.h2, x, P.phi, ulo, uhi, n, d, mblocks, vec, float(eps), oa,
+        P.status);
+  }
+  VIP_LAUNCH_CHECK();
   if (noise) {
     if (n <= kCholMax) {
       cholesky_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, P.Lf, n, 6, P.status);
@@ -1608,35 +1649,11 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       VIP_LAUNCH_CHECK();
       xin = P.xi;
     }
-    update_kernel<true><<<ugrid, dim3(256), 0, s>>>(P.K, P.Lf, g, P.xc, vq, xin, P.s, P.h2, x, P.phi,
-                                                    lo, hi, n, d, float(eps),
-                                                    float(std::sqrt(2.0 * eps)), P.status);
-  } else {
-    const int mblocks = (n + UM - 1) / UM;
-    const long long ntiles = (long long)mblocks * ((d + UN - 1) / UN);
-    // float4 staging needs rows of a multiple of 4 floats and 16-byte aligned bases
-    const int vec = (d % 4 == 0) && (n % 4 == 0) && (reinterpret_cast<uintptr_t>(g) % 16 == 0) &&
-                    (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
-                    (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
-    if (split_update) {
-      const int npairs = P.ldk / 2;
-      const int bvec = d % 4 == 0 && reinterpret_cast<uintptr_t>(g) % 16 == 0 &&
-                       reinterpret_cast<uintptr_t>(x) % 16 == 0;
-      bpair_kernel<<<dim3(unsigned((P.dp + 1023) / 1024), unsigned(npairs)), dim3(256), 0, s>>>(
-          g, x, P.xbar, vq, P.h2, P.bph, P.bpl, n, d, P.dp, bvec);
-      VIP_LAUNCH_CHECK();
-      const int vblocks = (n + VM - 1) / VM;
-      const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
-      auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x3_kernel<false> : update_bf16x3_kernel<true>;
-      kern<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
-          P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, lo, hi, n, d,
-          vblocks, float(eps), oa, P.status);
-    } else {
-      auto *kern = oa.kind == VIP_OPT_SGD ? update_mfma_kernel<false> : update_mfma_kernel<true>;
-      kern<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
-          P.K, g, P.xc, vq, P.s, P.h2, x, P.phi, lo, hi, n, d, mblocks, vec, float(eps), oa,
-          P.status);
-    }
+    const int nvec = (d % 4 == 0) && (n % 4 == 0) &&
+                     (reinterpret_cast<uintptr_t>(xin) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(P.Lf) % 16 == 0);
+    noise_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
+        P.Lf, xin, vq, x, lo, hi, n, d, mblocks, nvec, float(std::sqrt(2.0 * eps)), P.status);
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;

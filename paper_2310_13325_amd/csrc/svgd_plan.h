@@ -17,7 +17,8 @@ struct SvgdPlan {
   uint32_t *hist = nullptr, *sel = nullptr;
   uint32_t *chol = nullptr;   // blocked Cholesky: [0] attempt failed, [1] every retry failed
   double *h2 = nullptr, *L = nullptr;
-  float *Lf = nullptr, *xi = nullptr, *phi = nullptr;
+  float *Lf = nullptr;   // FP32 copy of L, transposed (Lf[j][i] = L[i][j])
+  float *xi = nullptr, *phi = nullptr;
   uint16_t *khi = nullptr, *klo = nullptr;   // K split into BF16 pairs, rows of ldk
   uint32_t *bph = nullptr, *bpl = nullptr;   // B split, rows (j, j + 1) interleaved, pitch dp
   int ldk = 0;
