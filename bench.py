@@ -283,7 +283,7 @@ def c1_rate(ctx, vb, synth, torch, configs):
     return {"workload": "c1: 64x64 at 10 m, nt=500, 4 shots, 64 receivers, 8 particles, "
                         f"{steps} SVGD iterations (gradients + FP32-Gram SVGD step)",
             "svgd_iterations_per_s": round(steps / sec, 1),
-            "particle_gradients_per_s": round(steps * n / sec, 1), "tile": ctx.tile_for(S1["grid"])}
+            "particle_gradients_per_s": round(steps * n / sec, 1), "tile": ctx.tile_for(S1["grid"], n * prob.ns)}
 
 
 def c3_rate(ctx, vb, synth, torch, configs, autotune, fixed=None):

@@ -156,9 +156,12 @@ int vip_tile_count(void);
  * (grid points, interior plus a halo of 2 points per step on each side), rows
  * per thread, steps per launch.  VIP_E_ARG for an index out of range. */
 vip_status vip_tile_shape(int tile, int32_t shape[4]);
-/* The shape a single-problem call on `grid` would use with this context's
- * setting: -1 (one step per launch) or a blocked tile index. */
-vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int32_t *tile);
+/* The shape a single-problem call on `grid` over `pairs` (particle, shot)
+ * pairs per launch would use with this context's setting: -1 (one step per
+ * launch) or a blocked tile index.  pairs <= 0 stands for enough pairs to
+ * fill the GPU.  The automatic choice models a launch's time per shape; with
+ * fewer blocks than compute units it takes the shape that gives the most. */
+vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int64_t pairs, int32_t *tile);
 /* Human-readable name of a status code (static string). */
 const char *vip_status_string(int status);
 /* Library version, major*10000 + minor*100 + patch. */

@@ -152,7 +152,7 @@ def lib() -> ctypes.CDLL:
             "vip_svgd_step_ex": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl,
                                                 ctypes.POINTER(VipSvgdConfig), PR, vp, vp, sz]),
             "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
-            "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.POINTER(ctypes.c_int32)]),
+            "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
             "vip_advi_sample": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, i64, vp, vp]),
             "vip_advi_step": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, i64, vp, vp, dbl,
@@ -369,11 +369,12 @@ class Context:
         """-2 automatic, -1 one step per launch, 0.. a temporally blocked shape."""
         _check(lib().vip_set_tile(self._h, int(tile)), "vip_set_tile")
 
-    def tile_for(self, grid: "Grid") -> int:
-        """Tile index a single-problem call on `grid` uses (-1: one step per launch)."""
+    def tile_for(self, grid: "Grid", pairs: int = 0) -> int:
+        """Tile index a single-problem call on `grid` over `pairs` (particle, shot)
+        pairs per launch uses (-1: one step per launch; pairs 0: many)."""
         t = ctypes.c_int32(0)
         g = grid.c()
-        _check(lib().vip_tile_for_grid(self._h, ctypes.byref(g), ctypes.byref(t)),
+        _check(lib().vip_tile_for_grid(self._h, ctypes.byref(g), int(pairs), ctypes.byref(t)),
                "vip_tile_for_grid")
         return int(t.value)
 

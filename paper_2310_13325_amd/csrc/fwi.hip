@@ -464,36 +464,81 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int tile_count() { return kNumTiles; }
 
-// Default shape when no tuned choice exists: the fewest padded point-updates
-// per useful point-step (extended area / (covered interior x steps per launch),
-// with the waste of partial tiles counted).
-static double tile_cost(int c, int NX, int NZ) {
+// Default shape when no tuned choice exists, from a launch-time model fitted
+// to the c2 gradient (240 x 160 padded points, 1280 pairs) timed per shape:
+// blocks run in rounds of one per compute unit (two for shapes whose LDS
+// allows it, sharing the unit), and a block costs W per extended point-step
+// plus a fixed F for loading its tile and writing it back.  The fit gives
+// W = 7.0e-5 us and F = 8.1 us (per step, 112^2: 55.8 us measured, 56.7
+// modelled; 104^2: 65.0 / 63.2; 96^2 two per unit: 79.5 / 80.1).  The model
+// holds while every unit has blocks: a launch with fewer blocks than units is
+// bound by one block's latency, which the smaller shapes shorten, so there
+// the shape that gives the most blocks (up to two per unit) is taken.
+constexpr int kComputeUnits = 256;
+
+static int tile_blocks_per_cu(int c) {
   const TileCfg &t = kTiles[c];
-  const int ix = t.ex - 4 * t.tmax, iz = t.ez - 4 * t.tmax;
-  const double tiles = double((NX + ix - 1) / ix) * double((NZ + iz - 1) / iz);
-  const double work = tiles * t.ex * t.ez / (double(NX) * NZ);
-  const double traffic = (12.0 * work + 8.0) / t.tmax;
-  return std::max(work * 25.0 / 39.3, traffic / 5.0);   // VALU ops vs HBM bytes, per point-step
+  return 2 * 2 * (t.ez + 4) * (t.ex + 4) * int(sizeof(float)) <= 160 * 1024 ? 2 : 1;
 }
 
-int default_tile(int NX, int NZ) {
+static long long tile_blocks(int c, int NX, int NZ, long long pairs) {
+  const TileCfg &t = kTiles[c];
+  const int ix = t.ex - 4 * t.tmax, iz = t.ez - 4 * t.tmax;
+  return (long long)((NX + ix - 1) / ix) * ((NZ + iz - 1) / iz) * std::max(1LL, pairs);
+}
+
+// Modelled microseconds per time step of one launch over `pairs` pairs.
+static double tile_cost(int c, int NX, int NZ, long long pairs) {
+  constexpr double W = 7.0e-5, F = 8.1;
+  const TileCfg &t = kTiles[c];
+  const long long blocks = tile_blocks(c, NX, NZ, pairs);
+  const long long k = tile_blocks_per_cu(c);
+  const long long rounds = (blocks + kComputeUnits * k - 1) / (kComputeUnits * k);
+  const long long share = std::min(k, (blocks + kComputeUnits - 1) / kComputeUnits);
+  return double(rounds * share) * (W * t.ex * t.ez * t.tmax + F) / t.tmax;
+}
+
+// Better of two shapes for `pairs` pairs per launch (pairs <= 0: many).
+static bool tile_better(int c, int b, int NX, int NZ, long long pairs) {
+  if (pairs <= 0) pairs = 1LL << 20;
+  const long long nc = tile_blocks(c, NX, NZ, pairs), nb = tile_blocks(b, NX, NZ, pairs);
+  const bool fc = nc >= kComputeUnits, fb = nb >= kComputeUnits;
+  if (fc != fb) return fc;
+  if (!fc) {
+    const long long uc = std::min<long long>(nc, kComputeUnits * tile_blocks_per_cu(c));
+    const long long ub = std::min<long long>(nb, kComputeUnits * tile_blocks_per_cu(b));
+    if (uc != ub) return uc > ub;
+  }
+  return tile_cost(c, NX, NZ, pairs) < tile_cost(b, NX, NZ, pairs);
+}
+
+int default_tile(int NX, int NZ, long long pairs) {
   int best = 0;
   for (int c = 1; c < kNumTiles; ++c)
-    if (tile_cost(c, NX, NZ) < tile_cost(best, NX, NZ)) best = c;
+    if (tile_better(c, best, NX, NZ, pairs)) best = c;
   return best;
 }
 
-// One shape for a batch of problems: the least total estimated cost.
+// One shape for a batch of problems launched together: the least summed
+// modelled time when their blocks fill the units, else the most blocks.
 static int default_tile_multi(const std::vector<FwiDims> &Ds) {
+  if (Ds.size() == 1) return default_tile(Ds[0].NX, Ds[0].NZ, Ds[0].live);
   int best = 0;
   double best_cost = 1e300;
+  long long best_blocks = 0;
   for (int c = 0; c < kNumTiles; ++c) {
     double cost = 0.0;
-    for (const FwiDims &D : Ds) cost += tile_cost(c, D.NX, D.NZ) * double(D.N) * D.pairs * D.nt;
-    if (cost < best_cost) {
-      best_cost = cost;
-      best = c;
+    long long blocks = 0;
+    for (const FwiDims &D : Ds) {
+      const long long launches = (D.pairs + D.live - 1) / D.live;
+      cost += tile_cost(c, D.NX, D.NZ, D.live) * double(launches) * D.nt;
+      blocks += tile_blocks(c, D.NX, D.NZ, D.live);
     }
+    blocks = std::min<long long>(blocks, kComputeUnits * tile_blocks_per_cu(c));
+    const bool better = blocks >= kComputeUnits && best_blocks >= kComputeUnits
+                            ? cost < best_cost
+                            : blocks > best_blocks || (blocks == best_blocks && cost < best_cost);
+    if (better) best = c, best_cost = cost, best_blocks = blocks;
   }
   return best;
 }
@@ -1007,13 +1052,13 @@ vip_status vip_tile_shape(int tile, int32_t shape[4]) {
   return VIP_OK;
 }
 
-vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int32_t *tile) {
+vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int64_t pairs, int32_t *tile) {
   if (!ctx || !grid || !tile || grid->nx <= 0 || grid->nz <= 0 || grid->nb < 0) return VIP_E_ARG;
   if (ctx->tile >= -1) {
     *tile = ctx->tile;
   } else {
     const int NX = grid->nx + 2 * grid->nb, NZ = grid->nz + 2 * grid->nb;
-    *tile = (long long)NX * NZ < kMaxBlockedPoints ? default_tile(NX, NZ) : -1;
+    *tile = (long long)NX * NZ < kMaxBlockedPoints ? default_tile(NX, NZ, pairs) : -1;
   }
   return VIP_OK;
 }

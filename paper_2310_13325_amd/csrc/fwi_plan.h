@@ -50,7 +50,7 @@ inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // Largest padded grid (points) the temporally blocked kernel accepts.
 constexpr long long kMaxBlockedPoints = 1LL << 29;
-int default_tile(int NX, int NZ);   // fwi.hip
+int default_tile(int NX, int NZ, long long pairs);   // fwi.hip; pairs <= 0: many
 int tile_count();
 
 inline int default_rz(int NZ) { return NZ >= 96 ? 8 : (NZ >= 40 ? 4 : 2); }
@@ -119,7 +119,7 @@ inline vip_status make_dims(const vip_grid *grid, const vip_geometry *geom, int3
     d.nrows = int(std::unique(rows.begin(), rows.end()) - rows.begin());
   }
   d.rz = default_rz(d.NZ);
-  d.tile = d.N < kMaxBlockedPoints ? default_tile(d.NX, d.NZ) : -1;
+  d.tile = d.N < kMaxBlockedPoints ? default_tile(d.NX, d.NZ, d.live) : -1;
   d.inv_dx2 = 1.0 / (double(g.dx) * g.dx);
   d.inv_dz2 = 1.0 / (double(g.dz) * g.dz);
   d.cx = float(1.0 / (g.dx * g.dx));
