@@ -1201,92 +1201,73 @@ __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const 
 // BF16 Gram already puts into K; this is the update of the BF16 path.
 //
 // bpair_kernel forms B = G Q^-1 - Xc / h^2 once (Xc = x - xbar recomputed, the
-// centring kernel does not store it on this path) and splits it, rows j and
-// j + 1 interleaved as 32-bit pairs (the k order of a matrix-core operand),
-// rows padded with zeros to ldk and columns to dp.
-// Grid: y = pair p, x = 1024 columns per block, four per thread (16-byte
-// loads when d is a multiple of 4, and 16-byte stores: dp is a multiple of 8).
+// centring kernel does not store it on this path) and splits it.  Rows j and
+// j + 1 are packed into one 32-bit pair (the k order of a matrix-core
+// operand), and four consecutive pairs of one column are stored together:
+// word r of column a in group q (rows 8q .. 8q + 7) sits at (q dp + a) 4 + r,
+// so that a 16-byte load gives one lane's fragment of 8 k.  Rows are padded
+// with zeros to ldk and columns to dp.
+// Grid: y = group q, x = 256 columns per block, one per thread (each load
+// instruction of a wave reads 256 contiguous bytes of a row, each store
+// writes 1 KB contiguous).
 __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float *x,
                                                     const float *xbar, const float *vq,
                                                     const double *h2,
                                                     uint32_t *bph, uint32_t *bpl, int n,
-                                                    long long d, long long dp, int vec) {
-  const int p = int(blockIdx.y);
-  const long long a4 = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;   // my first column
-  if (a4 >= dp) return;
-  const float inv_h2 = float(1.0 / h2[0]);
-  float xb[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sc[4] = {1.0f, 1.0f, 1.0f, 1.0f};
-  const bool full = vec && a4 + 3 < d;
-  if (full) {
-    const float4 t = *reinterpret_cast<const float4 *>(xbar + a4);
-    xb[0] = t.x, xb[1] = t.y, xb[2] = t.z, xb[3] = t.w;
-    if (vq) {
-      const float4 u = *reinterpret_cast<const float4 *>(vq + a4);
-      sc[0] = u.x, sc[1] = u.y, sc[2] = u.z, sc[3] = u.w;
-    }
-  } else {
-    for (int c = 0; c < 4; ++c)
-      if (a4 + c < d) {
-        xb[c] = xbar[a4 + c];
-        if (vq) sc[c] = vq[a4 + c];
-      }
-  }
+                                                    long long d, long long dp) {
+  const int q = int(blockIdx.y);
+  const long long a = (long long)blockIdx.x * 256 + threadIdx.x;   // my column
+  if (a >= dp) return;
   uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+  if (a < d) {
+    const float inv_h2 = float(1.0 / h2[0]);
+    const float xb = xbar[a], sc = vq ? vq[a] : 1.0f;
+    float gv[8], xv[8];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int j = 2 * p + q;
-    if (j >= n) continue;
-    float gv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, xv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const long long row = (long long)j * d + a4;
-    if (full) {
-      const float4 tg = *reinterpret_cast<const float4 *>(g + row);
-      const float4 tx = *reinterpret_cast<const float4 *>(x + row);
-      gv[0] = tg.x, gv[1] = tg.y, gv[2] = tg.z, gv[3] = tg.w;
-      xv[0] = tx.x, xv[1] = tx.y, xv[2] = tx.z, xv[3] = tx.w;
-    } else {
-      for (int c = 0; c < 4; ++c)
-        if (a4 + c < d) {
-          gv[c] = g[row + c];
-          xv[c] = x[row + c];
-        }
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = 8 * q + jj;
+      const long long e = (long long)(j < n ? j : 0) * d + a;   // rows past n are not used
+      gv[jj] = g[e];
+      xv[jj] = x[e];
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (!full && a4 + c >= d) continue;
-      const float gs = vq ? gv[c] * sc[c] : gv[c];
-      const float xcv = xv[c] - xb[c];   // the centring kernel's Xc
-      const float b = fmaf(-xcv, inv_h2, gs);
+    for (int jj = 0; jj < 8; ++jj) {
+      if (8 * q + jj >= n) break;
+      const float gs = vq ? gv[jj] * sc : gv[jj];
+      const float b = fmaf(-(xv[jj] - xb), inv_h2, gs);   // x - xbar: the centring kernel's Xc
       const uint16_t hb = f32_to_bf16_rne(b);
       const uint16_t lb = f32_to_bf16_rne(b - bf16_to_f32(hb));
-      hw[c] |= uint32_t(hb) << (16 * q);
-      lw[c] |= uint32_t(lb) << (16 * q);
+      hw[jj >> 1] |= uint32_t(hb) << (16 * (jj & 1));
+      lw[jj >> 1] |= uint32_t(lb) << (16 * (jj & 1));
     }
   }
-  const long long o = (long long)p * dp + a4;
+  const long long o = ((long long)q * dp + a) * 4;
   *reinterpret_cast<uint4 *>(bph + o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
   *reinterpret_cast<uint4 *>(bpl + o) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
 }
 
-// Block: 256 particles x 256 coordinates, 8 waves (4 x 2) of 2 x 4 tiles of
+// Block: 128 particles x 256 coordinates, 4 waves (2 x 2) of 2 x 4 tiles of
 // 32 x 32 (v_mfma_f32_32x32x16_bf16, operand and result layout as in the Gram
-// kernel); the particle index j runs in stages of 32 through LDS, the next
-// stage prefetched into registers.  A = K rows i (K is symmetric) with 32
-// consecutive j from the split copy; a B fragment is four 32-bit pairs of
-// its column, kept column by column in LDS (16 pairs and 4 cells of padding
-// per column, so that the 16-byte fragment reads of 16 lanes meet distinct
-// banks) and read with one 16-byte load.  The three products go over all
-// eight tiles in turn, so that consecutive matrix instructions accumulate
-// into different tiles.
-constexpr int VM = 256, VN = 256, VK = 32, VKP = VK + 8, VBT = VK / 2 + 4, VT = 512;
+// kernel), 60 KB of LDS and at most 256 registers, so that two blocks share a
+// compute unit: one block's epilogue (HBM-bound) and barriers then overlap
+// the other's matrix instructions.  The particle index j runs in stages of
+// 32 through LDS, the next stage prefetched into registers.  A = K rows i (K
+// is symmetric) with 32 consecutive j from the split copy; a B fragment is
+// the four 32-bit pairs of one column and group, stored as such by
+// bpair_kernel and kept column by column in LDS (16 pairs and 4 cells of
+// padding per column, so that the 16-byte accesses of 8 consecutive lanes
+// meet distinct banks).  The three products go over all eight tiles in turn,
+// so that consecutive matrix instructions accumulate into different tiles.
+constexpr int VM = 128, VN = 256, VK = 32, VKP = VK + 8, VBT = VK / 2 + 4, VT = 256;
 template <bool RULE>
-__global__ __launch_bounds__(VT) void update_bf16x3_kernel(
+__global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void update_bf16x3_kernel(
     const uint16_t *khi, const uint16_t *klo, int ldk, const uint32_t *bph, const uint32_t *bpl,
     long long dp, const float *xbar, const float *s, const double *h2, float *x, float *phi,
     const float *lo, const float *hi, int n, long long d, int mblocks, float eps, OptArgs opt,
     uint32_t *status) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[VM][VKP];   // Ah[i][k] = hi(K[i0 + i][j0 + k])
   __shared__ __attribute__((aligned(16))) uint16_t Al[VM][VKP];
-  __shared__ __attribute__((aligned(16))) uint32_t Bh[VN][VBT];   // Bh[a][p] = pair j0 + 2p, + 1
+  __shared__ __attribute__((aligned(16))) uint32_t Bh[VN][VBT];   // Bh[a][p] = pair j0 / 2 + p
   __shared__ __attribute__((aligned(16))) uint32_t Bl[VN][VBT];
   const int per = int(gridDim.x) >> 3;
   const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
@@ -1297,12 +1278,10 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
 
-  // staging: A row t / 2, k half 16 (t % 2); B pair row lane % 16 and
-  // columns bcol + 16 h .. + 3 (h = 0, 1), bcol = 32 w + 4 (lane / 16): the
-  // transposed LDS stores of one instruction then meet 64 distinct banks
+  // staging: A row t / 2, k half 16 (t % 2); B column t, all four groups
   const int ar = t >> 1, ak = (t & 1) * 16;
-  const int bp = lane & 15, bcol = w * 32 + 4 * (lane >> 4);
-  uint4 pah[2], pal[2], pbh[2], pbl[2];
+  const bool bin = a0 + t < dp;   // dp is a multiple of 8: zero columns beyond it
+  uint4 pah[2], pal[2], pbh[4], pbl[4];
   auto load_stage = [&](int j0) {
     const int i = i0 + ar;
     if (i < n) {
@@ -1316,12 +1295,10 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
       pah[0] = pah[1] = pal[0] = pal[1] = make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      // dp is a multiple of 8: the 4 columns are all in or all out
-      const long long a = a0 + bcol + 16 * h;
-      const long long off = (long long)(j0 / 2 + bp) * dp + a;
-      pbh[h] = a < dp ? *reinterpret_cast<const uint4 *>(bph + off) : make_uint4(0, 0, 0, 0);
-      pbl[h] = a < dp ? *reinterpret_cast<const uint4 *>(bpl + off) : make_uint4(0, 0, 0, 0);
+    for (int h = 0; h < 4; ++h) {
+      const long long off = ((long long)(j0 / 8 + h) * dp + a0 + t) * 4;
+      pbh[h] = bin ? *reinterpret_cast<const uint4 *>(bph + off) : make_uint4(0, 0, 0, 0);
+      pbl[h] = bin ? *reinterpret_cast<const uint4 *>(bpl + off) : make_uint4(0, 0, 0, 0);
     }
   };
   auto store_stage = [&]() {
@@ -1330,16 +1307,9 @@ __global__ __launch_bounds__(VT) void update_bf16x3_kernel(
     *reinterpret_cast<uint4 *>(&Al[ar][ak]) = pal[0];
     *reinterpret_cast<uint4 *>(&Al[ar][ak + 8]) = pal[1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int c = bcol + 16 * h;
-      Bh[c][bp] = pbh[h].x;
-      Bh[c + 1][bp] = pbh[h].y;
-      Bh[c + 2][bp] = pbh[h].z;
-      Bh[c + 3][bp] = pbh[h].w;
-      Bl[c][bp] = pbl[h].x;
-      Bl[c + 1][bp] = pbl[h].y;
-      Bl[c + 2][bp] = pbl[h].z;
-      Bl[c + 3][bp] = pbl[h].w;
+    for (int h = 0; h < 4; ++h) {
+      *reinterpret_cast<uint4 *>(&Bh[t][4 * h]) = pbh[h];
+      *reinterpret_cast<uint4 *>(&Bl[t][4 * h]) = pbl[h];
     }
   };
 
@@ -1596,11 +1566,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
                   (reinterpret_cast<uintptr_t>(P.xc) % 16 == 0) &&
                   (reinterpret_cast<uintptr_t>(P.K) % 16 == 0);
   if (split_update) {
-    const int npairs = P.ldk / 2;
-    const int bvec = d % 4 == 0 && reinterpret_cast<uintptr_t>(g) % 16 == 0 &&
-                     reinterpret_cast<uintptr_t>(x) % 16 == 0;
-    bpair_kernel<<<dim3(unsigned((P.dp + 1023) / 1024), unsigned(npairs)), dim3(256), 0, s>>>(
-        g, x, P.xbar, vq, P.h2, P.bph, P.bpl, n, d, P.dp, bvec);
+    const int ngroups = P.ldk / 8;
+    bpair_kernel<<<dim3(unsigned((P.dp + 255) / 256), unsigned(ngroups)), dim3(256), 0, s>>>(
+        g, x, P.xbar, vq, P.h2, P.bph, P.bpl, n, d, P.dp);
     VIP_LAUNCH_CHECK();
     const int vblocks = (n + VM - 1) / VM;
     const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);

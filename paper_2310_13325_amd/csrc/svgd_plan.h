@@ -20,7 +20,7 @@ struct SvgdPlan {
   float *Lf = nullptr;   // FP32 copy of L, transposed (Lf[j][i] = L[i][j])
   float *xi = nullptr, *phi = nullptr;
   uint16_t *khi = nullptr, *klo = nullptr;   // K split into BF16 pairs, rows of ldk
-  uint32_t *bph = nullptr, *bpl = nullptr;   // B split, rows (j, j + 1) interleaved, pitch dp
+  uint32_t *bph = nullptr, *bpl = nullptr;   // B split: pairs of rows, 4 pairs of a column together
   int ldk = 0;
   long long dp = 0;
   int nbt = 0;
