@@ -47,6 +47,17 @@ using BufRsrc = __amdgpu_buffer_rsrc_t;
 __device__ __forceinline__ BufRsrc field_rsrc(const float *base, int n) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, n * 4, 0x00020000);
 }
+// The same over a base address that is the same for the whole wave, taken as
+// such: the compiler then keeps the descriptor in scalar registers even when
+// register pressure would otherwise move it to vector registers (and make
+// every access loop over the distinct descriptors of the wave).
+__device__ __forceinline__ BufRsrc field_rsrc_uniform(const float *base, int n) {
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(p));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(p >> 32));
+  return field_rsrc(reinterpret_cast<const float *>((uint64_t(hi) << 32) | lo),
+                    __builtin_amdgcn_readfirstlane(n));
+}
 // (The b32 builtins move raw 32-bit words, hence the bit casts.)
 __device__ __forceinline__ float field_load(BufRsrc r, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, 0));

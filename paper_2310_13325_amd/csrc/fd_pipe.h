@@ -1,0 +1,407 @@
+// Persistent, software-pipelined variant of the temporally blocked step kernel.
+//
+// The arithmetic of a tile is that of fd_block (the same operations in the same
+// order, so the results are bitwise the same); what changes is how a compute
+// unit moves from one tile to the next.  fd_block runs one block per tile, and
+// with one 112 x 112 block per compute unit its start (loading u, q and c of
+// the extended tile) and its end (writing the interior back, adding the
+// imaging partial) leave the unit idle: about 40 % of a block's time on the
+// 240 x 160 grid.  Here one block per compute unit stays resident and walks a
+// run of tiles; while it steps tile i the loads of tile i+1 are in flight:
+//
+//  * u of tile i+1 goes straight from memory into an LDS staging area
+//    (buffer loads with the LDS flag: no registers are held while they fly),
+//    laid out thread-major so that every thread later reads back only the
+//    words its own wave wrote;
+//  * q of tile i+1 goes into registers where the mode leaves room (forward,
+//    forward-with-store, recompute); the adjoint, whose imaging sum and a^n
+//    prefetch fill its registers, loads it once tile i is written back;
+//  * c of tile i+1 is usually that of tile i: a block's run is ordered with
+//    the pairs fastest at each tile position, and the pairs of one particle
+//    (its shots) are consecutive, so c is reloaded only when the particle or
+//    the position changes.
+//
+// Each XCD takes a contiguous range of tiles and each of its blocks a
+// contiguous run of that range.  The grid is one block per compute unit (the
+// LDS of one block exceeds half a unit's), so every block is resident from the
+// start.
+#pragma once
+
+#include "fd_block.h"
+
+namespace vip {
+
+// LDS of one persistent block.
+template <int EX, int EZ, int RZ, int TMAX>
+constexpr int pipe_lds_bytes() {
+  return 2 * (EZ + 4) * (EX + 4) * 4 + RZ * EX * (EZ / RZ) * 4 + 8 * EZ + 4 * TMAX;
+}
+
+template <int MODE, int EX, int EZ, int RZ, int TMAX, bool ISO>
+__global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
+  // The arguments are read through the kernel-argument segment pointer and,
+  // inside the tile loop, through a copy of it that the compiler cannot see
+  // through: it then reloads them (scalar loads) on each tile instead of
+  // holding them all in scalar registers across the loop, which would spill.
+  (void)args;
+  typedef const __attribute__((address_space(4))) BlockArgs KArgs;
+  KArgs *const kap = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+  KArgs &a = *kap;
+  constexpr int NTHREADS = EX * (EZ / RZ);
+  constexpr int H = 2 * TMAX;                 // halo width
+  constexpr int IX = EX - 2 * H, IZ = EZ - 2 * H;
+  constexpr int LW = EX + 4;                  // LDS row with 2 zero cells each side
+  constexpr bool ADJ = MODE == BMODE_ADJ;
+  constexpr bool TRACES = MODE == BMODE_FWD || MODE == BMODE_FWS;   // record receiver traces
+  constexpr bool STORE = MODE == BMODE_REC || MODE == BMODE_FWS;    // store a^n
+  constexpr bool PREQ = !ADJ;                 // q of the next tile prefetched into registers
+  static_assert(IX > 0 && IZ > 0 && EZ % RZ == 0 && RZ >= 2 && RZ <= 32, "tile shape");
+  static_assert(NTHREADS % 64 == 0, "whole waves");
+  static_assert(pipe_lds_bytes<EX, EZ, RZ, TMAX>() <= kLdsBytes, "LDS");
+  __shared__ float lds[2][EZ + 4][LW];
+  __shared__ float stage[RZ][NTHREADS];   // u of the next tile: row r of thread t at [r][t]
+  __shared__ float gzs[EZ];     // z damping of each extended-tile row (0 outside the grid)
+  __shared__ int rrs[EZ];       // receiver-row index of each extended-tile row (-1: none)
+  __shared__ float injs[TMAX];  // forward / recompute: source term w(t_n)/(dx dz) of each step
+
+  // This block's run of tiles: XCD x = blockIdx % 8 owns [x per, (x + 1) per),
+  // its j-th block the j-th of J runs of that range.  Tile index t stands for
+  // tile position t / npairs of local pair t % npairs.
+  const int J = int(gridDim.x) >> 3;
+  const int per = (a.total_tiles + 7) >> 3;
+  const int xbeg = (int(blockIdx.x) & 7) * per;
+  const int tend = min(a.total_tiles, xbeg + per);
+  int t = xbeg + (int(blockIdx.x) >> 3);
+  if (t >= tend) return;
+
+  const int NX = a.NX, NZ = a.NZ;
+  const int col = int(threadIdx.x) % EX;
+  const int strip = int(threadIdx.x) / EX;
+  const int zl0 = strip * RZ;              // first extended-tile row of my strip
+  const uint32_t row_bytes = uint32_t(NX) * 4u;
+
+  // once per block: zero the padding cells of both u buffers (every other cell
+  // is written before it is read); wavelet samples of this launch's steps
+  {
+    constexpr int PR = 4 * LW, PC = 4 * EZ;   // padding rows, padding columns
+    for (int e = threadIdx.x; e < 2 * (PR + PC); e += NTHREADS) {
+      const int b = e / (PR + PC), k = e - (e / (PR + PC)) * (PR + PC);
+      int row, colp;
+      if (k < PR) {
+        const int rr = k / LW;
+        row = rr < 2 ? rr : EZ + rr;        // rows 0, 1, EZ + 2, EZ + 3
+        colp = k - rr * LW;
+      } else {
+        const int cc = (k - PR) / EZ;
+        row = 2 + (k - PR) - cc * EZ;
+        colp = cc < 2 ? cc : LW - 4 + cc;   // columns 0, 1, LW - 2, LW - 1
+      }
+      lds[b][row][colp] = 0.0f;
+    }
+  }
+  if (!ADJ && int(threadIdx.x) < a.steps)
+    injs[threadIdx.x] = a.wavelet[a.n_start + int(threadIdx.x)] * a.inv_area;
+
+  // Tile t: local pair, position, extended-tile origin, my column's byte
+  // offset in a field (see fd_block for the wrap-around that the range check
+  // turns into zeros above, below and beside the grid).
+  auto tile_lp = [&](int tt) { return tt / a.tiles_per_pair; };
+  auto tile_pos = [&](int tt) { return tt - (tt / a.tiles_per_pair) * a.tiles_per_pair; };
+  auto tile_particle = [&](int tt) { return (a.pair0 + tile_lp(tt)) / a.ns; };
+  auto tile_off = [&](int tt) -> uint32_t {
+    const int pos = tile_pos(tt);
+    const int tzi = pos / a.tiles_x, txi = pos - (pos / a.tiles_x) * a.tiles_x;
+    const int X = txi * IX - H + col;
+    return (X >= 0 && X < NX) ? uint32_t((tzi * IZ - H + zl0) * NX + X) * 4u : 0x80000000u;
+  };
+  // u of tile tt straight into the staging area: wave w's lanes write
+  // stage[r][64 w .. 64 w + 63], i.e. thread t's row r lands at stage[r][t].
+  auto stage_u = [&](int tt) {
+    if (a.zero_in) return;
+    const uint32_t offn = tile_off(tt);
+    const BufRsrc ru = field_rsrc_uniform(a.u_in + tile_lp(tt) * a.in_stride, a.N);
+    // the wave's first thread, as a scalar, so the LDS addresses (M0) are too
+    const int wave0 = __builtin_amdgcn_readfirstlane(int(threadIdx.x) & ~63);
+    float *srow = &stage[0][wave0];
+#pragma unroll
+    for (int r = 0; r < RZ; ++r)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ru, srow + r * NTHREADS, 4,
+                                               int(offn + uint32_t(r) * row_bytes), 0, 0, 0);
+  };
+  auto load_q = [&](int tt, float (&qq)[RZ]) {
+    const uint32_t offn = tile_off(tt);
+    // zero initial state: a buffer of no records reads 0
+    const BufRsrc rq = field_rsrc_uniform(a.q_in + tile_lp(tt) * a.in_stride, a.zero_in ? 0 : a.N);
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) qq[r] = field_load(rq, offn + uint32_t(r) * row_bytes);
+  };
+  auto load_c = [&](int tt, float (&cv)[RZ]) {
+    const uint32_t offn = tile_off(tt);
+    const BufRsrc rc = field_rsrc_uniform(a.c + (long long)tile_particle(tt) * a.N, a.N);
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) cv[r] = field_load(rc, offn + uint32_t(r) * row_bytes);
+  };
+
+  float u[RZ], q[RZ], cc[RZ], acc[ADJ ? RZ : 1];
+  // q of the next tile: prefetched into qn (not the adjoint), or (adjoint)
+  // loaded into av once the last step's imaging term has used it
+  float qn[PREQ ? RZ : 1];
+  float av[ADJ ? RZ : 1];
+  int pb = 0;   // the LDS u buffer the next tile's u is published into
+  stage_u(t);
+  load_q(t, q);
+  load_c(t, cc);
+  bool first = true;
+  // What depends on the tile position only (the run changes position rarely:
+  // its tiles are the pairs at one position), kept from tile to tile.
+  int cur_pos = -1;
+  int Z0 = 0, X = 0, idx0 = 0;
+  bool xin = false;
+  uint32_t off0 = 0, own = 0;
+  float gr[RZ];   // sponge factor g = gz gx of my rows
+  int rec_r0 = -1, rec_id0 = 0;   // receivers in my strip: the first one in registers
+  uint32_t rec_rest = 0;          // (the common case of receivers along rows), any
+                                  // further ones take a table lookup per step
+  for (;;) {
+    KArgs *apt = kap;
+    asm volatile("" : "+s"(apt));
+    KArgs &a = *apt;
+    const int lp = tile_lp(t);
+    const int pos = tile_pos(t);
+    const int gp = a.pair0 + lp;
+    const int particle = gp / a.ns, shot = gp - (gp / a.ns) * a.ns;
+    const int sidx = a.src_idx[shot];
+    const bool newpos = pos != cur_pos;
+    if (newpos) {
+      const int tzi = pos / a.tiles_x, txi = pos - (pos / a.tiles_x) * a.tiles_x;
+      const int X0 = txi * IX - H;
+      Z0 = tzi * IZ - H;
+      X = X0 + col;
+      xin = X >= 0 && X < NX;
+      const bool xown = col >= H && col < H + IX && X < NX;
+      idx0 = (Z0 + zl0) * NX + X;    // grid index of my first row (rows follow at +NX)
+      off0 = tile_off(t);
+      own = 0;
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) {
+        const int Z = Z0 + zl0 + r;
+        const int zl = zl0 + r;
+        if (xown && Z < NZ && zl >= H && zl < H + IZ) own |= 1u << r;
+      }
+    }
+
+    // All loads of tile t have landed (vmcnt 0): u in the staging area, q and
+    // c in registers.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    if (!first) {
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) q[r] = PREQ ? qn[r] : av[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) u[r] = a.zero_in ? 0.0f : stage[r][threadIdx.x];
+    if (ADJ) {
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) acc[r] = 0.0f;
+    }
+    // row of my strip that holds the shot's source, or -1
+    int src_r = -1;
+    {
+      const int sz = sidx / NX, sx = sidx - (sidx / NX) * NX;
+      if (sx == X && sz >= Z0 + zl0 && sz < Z0 + zl0 + RZ) src_r = sz - (Z0 + zl0);
+    }
+    if (newpos) {
+      // every thread is done with the previous tile's row tables (on the
+      // first tile, the padding of the u buffers is being zeroed)
+      if (!first) __syncthreads();
+      for (int e = threadIdx.x; e < EZ; e += NTHREADS) {
+        const int Z = Z0 + e;
+        const bool zin = Z >= 0 && Z < NZ;
+        gzs[e] = zin ? a.gz[Z] : 0.0f;
+        rrs[e] = (zin && MODE != BMODE_REC) ? a.rrow[Z] : -1;   // receivers: traces or residual
+      }
+      __syncthreads();
+      cur_pos = pos;
+      const float gxv = xin ? a.gx[X] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) gr[r] = gzs[zl0 + r] * gxv;
+      rec_r0 = -1;
+      rec_id0 = 0;
+      rec_rest = 0;
+      if (MODE != BMODE_REC && xin) {
+#pragma unroll
+        for (int r = 0; r < RZ; ++r) {
+          const int rr = rrs[zl0 + r];
+          if (rr >= 0) {
+            const int rid = a.rmap[rr * NX + X];
+            if (rid >= 0) {
+              if (rec_r0 < 0) {
+                rec_r0 = r;
+                rec_id0 = rid;
+              } else {
+                rec_rest |= 1u << r;
+              }
+            }
+          }
+        }
+      }
+    }
+    first = false;
+    // Publish u into the buffer the previous tile's last step did not read:
+    // no thread reads it until the barrier that opens step 0, and every
+    // thread writes only its own cells, which only it wrote before.
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) lds[pb][zl0 + r + 2][col + 2] = u[r];
+    const int tnext = t + J;
+    const bool more = tnext < tend;
+    // the next tile's loads fly while this tile steps (my staging words are
+    // free: their values are in u)
+    if (more) {
+      stage_u(tnext);
+      if constexpr (PREQ) load_q(tnext, qn);
+    }
+
+    // Adjoint imaging, one step late, as in fd_block.
+    const long long seg_pair = lp * a.seg_stride;
+    const uint32_t off_av = own ? off0 : 0x80000000u;
+    float rv = 0.0f, rvn = 0.0f;
+    if (ADJ) {
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) av[r] = 0.0f;
+      if (rec_r0 >= 0) rv = a.rho[lp * a.rho_stride + (long long)(a.n_start + 1) * a.nr + rec_id0];
+    }
+
+    for (int s = 0; s < a.steps; ++s) {
+      const int cur = (s + pb) & 1, nxt = cur ^ 1;
+      const int n = ADJ ? a.n_start - s : a.n_start + s;
+      if (ADJ && s + 1 < a.steps && rec_r0 >= 0)
+        rvn = a.rho[lp * a.rho_stride + (long long)n * a.nr + rec_id0];
+      // lds[cur] holds the current u; lds[nxt] is no longer read.  A plain
+      // barrier after the LDS writes: __syncthreads() would also wait for
+      // every vector memory operation in flight, the next tile's staging
+      // loads among them, since those write LDS.
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      if (!ADJ) {
+        if (src_r >= 0) {
+          const float f = injs[s];
+#pragma unroll
+          for (int r = 0; r < RZ; ++r)
+            if (r == src_r) q[r] = fmaf(cc[r], f, q[r]);
+        }
+      } else {
+        if (rec_r0 >= 0) {
+#pragma unroll
+          for (int r = 0; r < RZ; ++r)
+            if (r == rec_r0) q[r] = fmaf(cc[r], rv, q[r]);
+        }
+        if (rec_rest) {
+#pragma unroll
+          for (int r = 0; r < RZ; ++r) {
+            if ((rec_rest >> r) & 1u) {
+              const int rid = a.rmap[rrs[zl0 + r] * NX + X];
+              const float rho = a.rho[lp * a.rho_stride + (long long)(n + 1) * a.nr + rid];
+              q[r] = fmaf(cc[r], rho, q[r]);
+            }
+          }
+        }
+      }
+      uint32_t off_s = ADJ ? off_av : off0;
+      if (STORE || ADJ) asm volatile("" : "+v"(off_s));
+      BufRsrc rseg;
+      if (STORE || ADJ)
+        rseg = field_rsrc_uniform(a.seg + seg_pair + (long long)(n - a.seg_n0) * a.N, a.N);
+      float prev1 = lds[cur][zl0 + 1][col + 2];   // u at row zl0 - 1
+      float prev2 = lds[cur][zl0][col + 2];       // u at row zl0 - 2
+      const float nextA = lds[cur][zl0 + RZ + 2][col + 2];   // row zl0 + RZ
+      const float nextB = lds[cur][zl0 + RZ + 3][col + 2];   // row zl0 + RZ + 1
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) {
+        const int zl = zl0 + r;
+        const float uc = u[r];
+        if (ADJ) {
+          acc[r] = fmaf(uc, av[r], acc[r]);
+          av[r] = field_load(rseg, off_s + uint32_t(r) * row_bytes);
+        }
+        const float dn1 = (r + 1 < RZ) ? u[r + 1] : nextA;
+        const float dn2 = (r + 2 < RZ) ? u[r + 2] : (r + 2 == RZ ? nextA : nextB);
+        const float xm1 = lds[cur][zl + 2][col + 1], xp1 = lds[cur][zl + 2][col + 3];
+        const float xm2 = lds[cur][zl + 2][col], xp2 = lds[cur][zl + 2][col + 4];
+        float lap;
+        if (ISO) {
+          const float s1 = (xm1 + xp1) + (prev1 + dn1), s2 = (xm2 + xp2) + (prev2 + dn2);
+          lap = fmaf(a.w1x, fmaf(-4.0f, uc, s1), a.w2x * fmaf(-4.0f, uc, s2));
+        } else {
+          const float d1x = fmaf(-2.0f, uc, xm1 + xp1), d2x = fmaf(-2.0f, uc, xm2 + xp2);
+          const float d1z = fmaf(-2.0f, uc, prev1 + dn1), d2z = fmaf(-2.0f, uc, prev2 + dn2);
+          lap = fmaf(a.w1x, d1x, fmaf(a.w2x, d2x, fmaf(a.w1z, d1z, a.w2z * d2z)));
+        }
+        if (STORE && ((own >> r) & 1u))
+          field_store(rseg, off_s + uint32_t(r) * row_bytes, lap);
+        const float qn1 = gr[r] * fmaf(cc[r], lap, q[r]);
+        const float un = fmaf(gr[r], uc, qn1);
+        prev2 = prev1;
+        prev1 = uc;
+        u[r] = un;
+        q[r] = qn1;
+        lds[nxt][zl + 2][col + 2] = un;
+      }
+      if (TRACES) {
+        if (rec_r0 >= 0 && ((own >> rec_r0) & 1u)) {
+          const float val = lds[nxt][zl0 + rec_r0 + 2][col + 2];
+          float *d = a.data + lp * a.data_stride;
+          d[(long long)(n + 1) * a.nr + rec_id0] = val;
+          if (n == 0) d[rec_id0] = 0.0f;   // u^0 = 0
+        }
+        if (rec_rest & own) {
+          float *d = a.data + lp * a.data_stride;
+#pragma unroll
+          for (int r = 0; r < RZ; ++r) {
+            if (((rec_rest & own) >> r) & 1u) {
+              const int rid = a.rmap[rrs[zl0 + r] * NX + X];
+              d[(long long)(n + 1) * a.nr + rid] = u[r];
+              if (n == 0) d[rid] = 0.0f;
+            }
+          }
+        }
+      }
+      if (ADJ) {
+        if (src_r >= 0 && ((own >> src_r) & 1u)) {
+          const float f = a.wavelet[n] * a.inv_area;
+#pragma unroll
+          for (int r = 0; r < RZ; ++r)
+            if (r == src_r) acc[r] = fmaf(u[r], f, acc[r]);
+        }
+        rv = rvn;
+      }
+    }
+    pb = (pb + a.steps) & 1;   // the buffer the last step wrote, not read
+    if (ADJ) {
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) acc[r] = fmaf(u[r], av[r], acc[r]);   // the last step's term
+    }
+    // The next tile's c (when it differs) and the adjoint's q go out before
+    // the write-back, into registers this tile no longer needs.
+    if (more) {
+      if (tile_particle(tnext) != particle || tile_pos(tnext) != pos) load_c(tnext, cc);
+      if constexpr (!PREQ) load_q(tnext, av);
+    }
+    // write back the owned interior: u, q and (adjoint) the launch's imaging
+    // partial into the FP64 sum (one add per point and launch, so the
+    // no-return atomic adds what a read, add and store would)
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) {
+      if (!((own >> r) & 1u)) continue;
+      const int i = idx0 + r * NX;
+      if (a.u_out) {
+        a.u_out[lp * a.out_stride + i] = u[r];
+        a.q_out[lp * a.out_stride + i] = q[r];
+      }
+      if (ADJ)
+        __hip_atomic_fetch_add(a.acc64 + lp * a.acc64_stride + i, double(acc[r]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!more) break;
+    t = tnext;
+  }
+}
+
+}  // namespace vip

@@ -154,8 +154,11 @@ vip_status vip_create(vip_ctx **out, int device, void *stream) {
   if (device < 0 || device >= count) return VIP_E_ARG;
   VIP_TRY_HIP(hipSetDevice(device));
   VIP_TRY(vip_noalloc_setup(device));
+  int cus = 0;
+  VIP_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   vip_ctx *ctx = new vip_ctx();
   ctx->device = device;
+  ctx->cus = cus;
   ctx->user = static_cast<hipStream_t>(stream);
   ctx->active = ctx->user;
   hipError_t e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);

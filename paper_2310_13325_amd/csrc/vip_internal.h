@@ -79,6 +79,7 @@ struct vip_timing_run {
 
 struct vip_ctx {
   int device = 0;
+  int cus = 0;     // compute units of the device
   bool timing = false;
   std::vector<vip_timing_run> runs;     // recorded, not yet read
   std::vector<hipEvent_t> event_pool;   // free events

@@ -22,7 +22,7 @@ GRAD_TOL = 1e-4
 LOGPOST_TOL = 1e-5
 
 
-TILES = [-1] + list(range(6))
+TILES = [-1] + list(range(7))
 
 
 def test_ricker_matches_oracle():
@@ -125,7 +125,7 @@ def test_grad_ragged_segments_and_chunks(tile):
     c.set_tile(-2)
 
 
-@pytest.mark.parametrize("tile", [-1, 0, 2])
+@pytest.mark.parametrize("tile", [-1, 0, 2, 6])
 def test_grad_stored_tail_segment(tile):
     """The forward sweep keeps a^n of the last S steps (the blocked kernel stores
     them as it goes, the one-step kernel recomputes them from a checkpoint):
@@ -163,7 +163,7 @@ def test_grad_stored_tail_segment(tile):
     c.set_tile(-2)
 
 
-@pytest.mark.parametrize("tile", [-1, 0, 2])
+@pytest.mark.parametrize("tile", [-1, 0, 2, 6])
 def test_minibatch_shot_subsets_match_oracle(tile):
     """Section 2.4 minibatches: a subset of the shots, read in place from the
     full d_obs, scaled by ns / b (through sigma); every shot in another order
