@@ -65,7 +65,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 # imaging product-sum z a (2).
 FLOPS_PER_POINT_STEP = {"forward": 18.0, "recompute": 18.0, "adjoint": 20.0,
                         "forward_store": 18.0}
-COUNTERS = os.path.join(ROOT, "profiles", "fd_block_c2_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "fd_pipe_c2_counters.json")
 STEP_SOURCES = [os.path.join(ROOT, "paper_2310_13325_amd", "csrc", f)
                 for f in ("fwi.hip", "fd_block.h", "fd_block_body.inc", "fd_pipe.h")]
 
@@ -536,7 +536,8 @@ def main():
     tile = ctx.tile_for(S["grid"])
     if tile >= 0:
         sh = vb.tile_shape(tile)
-        kname = (f"fd_block (temporally blocked, {sh['ex']}x{sh['ez']} extended tile, "
+        kname = (f"{'fd_pipe (persistent, ' if sh['persistent'] else 'fd_block ('}"
+                 f"temporally blocked, {sh['ex']}x{sh['ez']} extended tile, "
                  f"up to {sh['tmax']} steps per launch)")
     else:
         kname = "fd_step (one step per launch)"

@@ -156,6 +156,12 @@ int vip_tile_count(void);
  * (grid points, interior plus a halo of 2 points per step on each side), rows
  * per thread, steps per launch.  VIP_E_ARG for an index out of range. */
 vip_status vip_tile_shape(int tile, int32_t shape[4]);
+/* 1 if blocked tile `tile` runs persistently (one resident block per compute
+ * unit walking a run of tiles, the next tile's state loaded while the current
+ * one steps; the same arithmetic, and bitwise the same results, as the
+ * non-persistent tile of the same shape), 0 if one block runs per tile,
+ * VIP_E_ARG for an index out of range. */
+int vip_tile_persistent(int tile);
 /* The shape a single-problem call on `grid` over `pairs` (particle, shot)
  * pairs per launch would use with this context's setting: -1 (one step per
  * launch) or a blocked tile index.  pairs <= 0 stands for enough pairs to

@@ -152,6 +152,7 @@ def lib() -> ctypes.CDLL:
             "vip_svgd_step_ex": (ctypes.c_int, [vp, i32, i64, vp, vp, dbl,
                                                 ctypes.POINTER(VipSvgdConfig), PR, vp, vp, sz]),
             "vip_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+            "vip_tile_persistent": (ctypes.c_int, [ctypes.c_int]),
             "vip_tile_for_grid": (ctypes.c_int, [vp, G, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
             "vip_read_timing": (ctypes.c_int, [vp, ctypes.POINTER(VipTiming)]),
             "vip_advi_sample": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, i64, vp, vp]),
@@ -185,7 +186,9 @@ def tile_shape(tile: int) -> dict:
     """Extended width/height, rows per thread and steps per launch of a blocked tile."""
     a = (ctypes.c_int32 * 4)()
     _check(lib().vip_tile_shape(int(tile), a), "vip_tile_shape")
-    return {"ex": a[0], "ez": a[1], "rz": a[2], "tmax": a[3]}
+    persistent = lib().vip_tile_persistent(int(tile))
+    _check(min(persistent, 0), "vip_tile_persistent")
+    return {"ex": a[0], "ez": a[1], "rz": a[2], "tmax": a[3], "persistent": bool(persistent)}
 
 
 # ----------------------------------------------------------------------------

@@ -1085,6 +1085,11 @@ vip_status vip_tile_shape(int tile, int32_t shape[4]) {
   return VIP_OK;
 }
 
+int vip_tile_persistent(int tile) {
+  if (tile < 0 || tile >= tile_count()) return VIP_E_ARG;
+  return kTiles[tile].pipe;
+}
+
 vip_status vip_tile_for_grid(const vip_ctx *ctx, const vip_grid *grid, int64_t pairs, int32_t *tile) {
   if (!ctx || !grid || !tile || grid->nx <= 0 || grid->nz <= 0 || grid->nb < 0) return VIP_E_ARG;
   if (ctx->tile >= -1) {
