@@ -27,6 +27,8 @@
 // start.
 #pragma once
 
+#include <type_traits>
+
 #include "fd_block.h"
 
 namespace vip {
@@ -37,16 +39,45 @@ constexpr int pipe_lds_bytes() {
   return 2 * (EZ + 4) * (EX + 4) * 4 + RZ * EX * (EZ / RZ) * 4 + 8 * EZ + 4 * TMAX;
 }
 
-template <int MODE, int EX, int EZ, int RZ, int TMAX, bool ISO>
-__global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
+// MULTI: the launch carries several problems (MultiArgs: tile ranges
+// [start[p], start[p + 1]) of one shape and one sweep mode) and a block's run
+// of tiles may cross from one problem to the next; otherwise one problem
+// (BlockArgs).
+template <bool MULTI>
+using PipeParams = typename std::conditional<MULTI, MultiArgs, BlockArgs>::type;
+
+template <int MODE, int EX, int EZ, int RZ, int TMAX, bool ISO, bool MULTI>
+__global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args) {
   // The arguments are read through the kernel-argument segment pointer and,
   // inside the tile loop, through a copy of it that the compiler cannot see
   // through: it then reloads them (scalar loads) on each tile instead of
   // holding them all in scalar registers across the loop, which would spill.
   (void)args;
   typedef const __attribute__((address_space(4))) BlockArgs KArgs;
-  KArgs *const kap = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-  KArgs &a = *kap;
+  typedef const __attribute__((address_space(4))) PipeParams<MULTI> KParams;
+  KParams *const kp0 = (KParams *)__builtin_amdgcn_kernarg_segment_ptr();
+  // tiles of the launch, the problem of tile tt and its first tile, its arguments
+  auto total_of = [](KParams *kp) -> int {
+    if constexpr (MULTI) return kp->start[kp->nprob];
+    else return kp->total_tiles;
+  };
+  auto prob_of = [](KParams *kp, int tt) -> int {
+    if constexpr (MULTI) {
+      int p = 0;
+      while (p + 1 < kp->nprob && tt >= kp->start[p + 1]) ++p;
+      return p;
+    } else {
+      return 0;
+    }
+  };
+  auto first_of = [](KParams *kp, int p) -> int {
+    if constexpr (MULTI) return kp->start[p];
+    else return 0;
+  };
+  auto args_of = [](KParams *kp, int p) -> KArgs & {
+    if constexpr (MULTI) return kp->a[p];
+    else return *kp;
+  };
   constexpr int NTHREADS = EX * (EZ / RZ);
   constexpr int H = 2 * TMAX;                 // halo width
   constexpr int IX = EX - 2 * H, IZ = EZ - 2 * H;
@@ -68,17 +99,16 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
   // its j-th block the j-th of J runs of that range.  Tile index t stands for
   // tile position t / npairs of local pair t % npairs.
   const int J = int(gridDim.x) >> 3;
-  const int per = (a.total_tiles + 7) >> 3;
+  const int total = total_of(kp0);
+  const int per = (total + 7) >> 3;
   const int xbeg = (int(blockIdx.x) & 7) * per;
-  const int tend = min(a.total_tiles, xbeg + per);
+  const int tend = min(total, xbeg + per);
   int t = xbeg + (int(blockIdx.x) >> 3);
   if (t >= tend) return;
 
-  const int NX = a.NX, NZ = a.NZ;
   const int col = int(threadIdx.x) % EX;
   const int strip = int(threadIdx.x) / EX;
   const int zl0 = strip * RZ;              // first extended-tile row of my strip
-  const uint32_t row_bytes = uint32_t(NX) * 4u;
 
   // once per block: zero the padding cells of both u buffers (every other cell
   // is written before it is read); wavelet samples of this launch's steps
@@ -99,47 +129,49 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
       lds[b][row][colp] = 0.0f;
     }
   }
-  if (!ADJ && int(threadIdx.x) < a.steps)
-    injs[threadIdx.x] = a.wavelet[a.n_start + int(threadIdx.x)] * a.inv_area;
 
-  // Tile t: local pair, position, extended-tile origin, my column's byte
-  // offset in a field (see fd_block for the wrap-around that the range check
-  // turns into zeros above, below and beside the grid).
-  auto tile_lp = [&](int tt) { return tt / a.tiles_per_pair; };
-  auto tile_pos = [&](int tt) { return tt - (tt / a.tiles_per_pair) * a.tiles_per_pair; };
-  auto tile_particle = [&](int tt) { return (a.pair0 + tile_lp(tt)) / a.ns; };
-  auto tile_off = [&](int tt) -> uint32_t {
-    const int pos = tile_pos(tt);
+  // Local tile lt of problem a: local pair, position, my column's byte offset
+  // in a field (see fd_block for the wrap-around that the range check turns
+  // into zeros above, below and beside the grid).
+  auto tile_lp = [](KArgs &a, int lt) { return lt / a.tiles_per_pair; };
+  auto tile_pos = [](KArgs &a, int lt) { return lt - (lt / a.tiles_per_pair) * a.tiles_per_pair; };
+  auto tile_particle = [&](KArgs &a, int lt) { return (a.pair0 + tile_lp(a, lt)) / a.ns; };
+  auto tile_off = [&](KArgs &a, int lt) -> uint32_t {
+    const int pos = tile_pos(a, lt);
     const int tzi = pos / a.tiles_x, txi = pos - (pos / a.tiles_x) * a.tiles_x;
     const int X = txi * IX - H + col;
-    return (X >= 0 && X < NX) ? uint32_t((tzi * IZ - H + zl0) * NX + X) * 4u : 0x80000000u;
+    return (X >= 0 && X < a.NX) ? uint32_t((tzi * IZ - H + zl0) * a.NX + X) * 4u : 0x80000000u;
   };
-  // u of tile tt straight into the staging area: wave w's lanes write
+  // u of a tile straight into the staging area: wave w's lanes write
   // stage[r][64 w .. 64 w + 63], i.e. thread t's row r lands at stage[r][t].
-  auto stage_u = [&](int tt) {
+  auto stage_u = [&](KArgs &a, int lt) {
     if (a.zero_in) return;
-    const uint32_t offn = tile_off(tt);
-    const BufRsrc ru = field_rsrc_uniform(a.u_in + tile_lp(tt) * a.in_stride, a.N);
+    const uint32_t offn = tile_off(a, lt);
+    const uint32_t rb = uint32_t(a.NX) * 4u;
+    const BufRsrc ru = field_rsrc_uniform(a.u_in + tile_lp(a, lt) * a.in_stride, a.N);
     // the wave's first thread, as a scalar, so the LDS addresses (M0) are too
     const int wave0 = __builtin_amdgcn_readfirstlane(int(threadIdx.x) & ~63);
     float *srow = &stage[0][wave0];
 #pragma unroll
     for (int r = 0; r < RZ; ++r)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(ru, srow + r * NTHREADS, 4,
-                                               int(offn + uint32_t(r) * row_bytes), 0, 0, 0);
+                                               int(offn + uint32_t(r) * rb), 0, 0, 0);
   };
-  auto load_q = [&](int tt, float (&qq)[RZ]) {
-    const uint32_t offn = tile_off(tt);
+  auto load_q = [&](KArgs &a, int lt, float (&qq)[RZ]) {
+    const uint32_t offn = tile_off(a, lt);
+    const uint32_t rb = uint32_t(a.NX) * 4u;
     // zero initial state: a buffer of no records reads 0
-    const BufRsrc rq = field_rsrc_uniform(a.q_in + tile_lp(tt) * a.in_stride, a.zero_in ? 0 : a.N);
+    const BufRsrc rq =
+        field_rsrc_uniform(a.q_in + tile_lp(a, lt) * a.in_stride, a.zero_in ? 0 : a.N);
 #pragma unroll
-    for (int r = 0; r < RZ; ++r) qq[r] = field_load(rq, offn + uint32_t(r) * row_bytes);
+    for (int r = 0; r < RZ; ++r) qq[r] = field_load(rq, offn + uint32_t(r) * rb);
   };
-  auto load_c = [&](int tt, float (&cv)[RZ]) {
-    const uint32_t offn = tile_off(tt);
-    const BufRsrc rc = field_rsrc_uniform(a.c + (long long)tile_particle(tt) * a.N, a.N);
+  auto load_c = [&](KArgs &a, int lt, float (&cv)[RZ]) {
+    const uint32_t offn = tile_off(a, lt);
+    const uint32_t rb = uint32_t(a.NX) * 4u;
+    const BufRsrc rc = field_rsrc_uniform(a.c + (long long)tile_particle(a, lt) * a.N, a.N);
 #pragma unroll
-    for (int r = 0; r < RZ; ++r) cv[r] = field_load(rc, offn + uint32_t(r) * row_bytes);
+    for (int r = 0; r < RZ; ++r) cv[r] = field_load(rc, offn + uint32_t(r) * rb);
   };
 
   float u[RZ], q[RZ], cc[RZ], acc[ADJ ? RZ : 1];
@@ -148,14 +180,20 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
   float qn[PREQ ? RZ : 1];
   float av[ADJ ? RZ : 1];
   int pb = 0;   // the LDS u buffer the next tile's u is published into
-  stage_u(t);
-  load_q(t, q);
-  load_c(t, cc);
+  {
+    const int p0 = prob_of(kp0, t);
+    KArgs &a0 = args_of(kp0, p0);
+    const int lt0 = t - first_of(kp0, p0);
+    stage_u(a0, lt0);
+    load_q(a0, lt0, q);
+    load_c(a0, lt0, cc);
+  }
   bool first = true;
-  // What depends on the tile position only (the run changes position rarely:
-  // its tiles are the pairs at one position), kept from tile to tile.
-  int cur_pos = -1;
-  int Z0 = 0, X = 0, idx0 = 0;
+  // What depends on the problem and tile position only, kept from tile to
+  // tile (the 32 blocks of an XCD step neighbouring tiles, so a block's next
+  // tile is often at the same position of another pair).
+  int cur_p = -1, cur_pos = -1;
+  int Z0 = 0, X = 0;
   bool xin = false;
   uint32_t off0 = 0, own = 0;
   float gr[RZ];   // sponge factor g = gz gx of my rows
@@ -163,15 +201,20 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
   uint32_t rec_rest = 0;          // (the common case of receivers along rows), any
                                   // further ones take a table lookup per step
   for (;;) {
-    KArgs *apt = kap;
-    asm volatile("" : "+s"(apt));
-    KArgs &a = *apt;
-    const int lp = tile_lp(t);
-    const int pos = tile_pos(t);
+    KParams *kp = kp0;
+    asm volatile("" : "+s"(kp));
+    const int prob = prob_of(kp, t);
+    KArgs &a = args_of(kp, prob);
+    const int lt = t - first_of(kp, prob);
+    const int NX = a.NX, NZ = a.NZ;
+    const uint32_t row_bytes = uint32_t(NX) * 4u;
+    const int lp = tile_lp(a, lt);
+    const int pos = tile_pos(a, lt);
     const int gp = a.pair0 + lp;
     const int particle = gp / a.ns, shot = gp - (gp / a.ns) * a.ns;
     const int sidx = a.src_idx[shot];
-    const bool newpos = pos != cur_pos;
+    const bool newprob = prob != cur_p;
+    const bool newpos = newprob || pos != cur_pos;
     if (newpos) {
       const int tzi = pos / a.tiles_x, txi = pos - (pos / a.tiles_x) * a.tiles_x;
       const int X0 = txi * IX - H;
@@ -179,8 +222,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
       X = X0 + col;
       xin = X >= 0 && X < NX;
       const bool xown = col >= H && col < H + IX && X < NX;
-      idx0 = (Z0 + zl0) * NX + X;    // grid index of my first row (rows follow at +NX)
-      off0 = tile_off(t);
+      off0 = tile_off(a, lt);
       own = 0;
 #pragma unroll
       for (int r = 0; r < RZ; ++r) {
@@ -219,7 +261,11 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
         gzs[e] = zin ? a.gz[Z] : 0.0f;
         rrs[e] = (zin && MODE != BMODE_REC) ? a.rrow[Z] : -1;   // receivers: traces or residual
       }
+      // wavelet samples of this launch's steps (forward, recompute)
+      if (!ADJ && newprob && int(threadIdx.x) < a.steps)
+        injs[threadIdx.x] = a.wavelet[a.n_start + int(threadIdx.x)] * a.inv_area;
       __syncthreads();
+      cur_p = prob;
       cur_pos = pos;
       const float gxv = xin ? a.gx[X] : 0.0f;
 #pragma unroll
@@ -256,8 +302,11 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
     // the next tile's loads fly while this tile steps (my staging words are
     // free: their values are in u)
     if (more) {
-      stage_u(tnext);
-      if constexpr (PREQ) load_q(tnext, qn);
+      const int pn = prob_of(kp, tnext);
+      KArgs &an = args_of(kp, pn);
+      const int ltn = tnext - first_of(kp, pn);
+      stage_u(an, ltn);
+      if constexpr (PREQ) load_q(an, ltn, qn);
     }
 
     // Adjoint imaging, one step late, as in fd_block.
@@ -381,8 +430,15 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
     // The next tile's c (when it differs) and the adjoint's q go out before
     // the write-back, into registers this tile no longer needs.
     if (more) {
-      if (tile_particle(tnext) != particle || tile_pos(tnext) != pos) load_c(tnext, cc);
-      if constexpr (!PREQ) load_q(tnext, av);
+      // (the next tile's problem is looked up again rather than kept live
+      // across the steps)
+      KParams *kq = kp;
+      const int pn = prob_of(kq, tnext);
+      KArgs &an = args_of(kq, pn);
+      const int ltn = tnext - first_of(kq, pn);
+      if (pn != prob || tile_particle(an, ltn) != particle || tile_pos(an, ltn) != pos)
+        load_c(an, ltn, cc);
+      if constexpr (!PREQ) load_q(an, ltn, av);
     }
     // write back the owned interior: u, q and (adjoint) the launch's imaging
     // partial into the FP64 sum (one add per point and launch, so the
@@ -390,7 +446,10 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(BlockArgs args) {
 #pragma unroll
     for (int r = 0; r < RZ; ++r) {
       if (!((own >> r) & 1u)) continue;
-      const int i = idx0 + r * NX;
+      // grid index of row r: an owned point is on the grid, so off0 is 4 times
+      // the index of my first row taken modulo 2^32; that row may lie above
+      // the grid (a negative index), hence the signed division
+      const int i = int(off0) / 4 + r * NX;
       if (a.u_out) {
         a.u_out[lp * a.out_stride + i] = u[r];
         a.q_out[lp * a.out_stride + i] = q[r];

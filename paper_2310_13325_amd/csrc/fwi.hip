@@ -576,11 +576,11 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
   if (tc.pipe) {
     // one resident block per compute unit, a multiple of the 8 XCDs
     const dim3 grid(unsigned(std::max(8, ctx->cus / 8 * 8)));
-#define VIP_PIPE_MODES(EX, EZ, RZ, TM, ISO)                                                   \
-  if (mode == BMODE_FWD) fd_pipe<BMODE_FWD, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);        \
-  else if (mode == BMODE_REC) fd_pipe<BMODE_REC, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);   \
-  else if (mode == BMODE_FWS) fd_pipe<BMODE_FWS, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);   \
-  else fd_pipe<BMODE_ADJ, EX, EZ, RZ, TM, ISO><<<grid, block, 0, s>>>(a);
+#define VIP_PIPE_MODES(EX, EZ, RZ, TM, ISO)                                                      \
+  if (mode == BMODE_FWD) fd_pipe<BMODE_FWD, EX, EZ, RZ, TM, ISO, false><<<grid, block, 0, s>>>(a);      \
+  else if (mode == BMODE_REC) fd_pipe<BMODE_REC, EX, EZ, RZ, TM, ISO, false><<<grid, block, 0, s>>>(a); \
+  else if (mode == BMODE_FWS) fd_pipe<BMODE_FWS, EX, EZ, RZ, TM, ISO, false><<<grid, block, 0, s>>>(a); \
+  else fd_pipe<BMODE_ADJ, EX, EZ, RZ, TM, ISO, false><<<grid, block, 0, s>>>(a);
     if (tc.ex == 112 && tc.ez == 112 && tc.rz == 14 && tc.tmax == 8) {
       if (a.iso) {
         VIP_PIPE_MODES(112, 112, 14, 8, true)
@@ -635,8 +635,32 @@ static vip_status launch_multi(vip_ctx *ctx, int cfg,
   if (acc > (1LL << 30)) return VIP_E_UNSUPPORTED;
   m.start[m.nprob] = int(acc);
   const TileCfg &tc = kTiles[cfg];
-  const dim3 grid(unsigned((acc + 7) / 8 * 8)), block(unsigned(tc.ex * (tc.ez / tc.rz)));
+  const dim3 block(unsigned(tc.ex * (tc.ez / tc.rz)));
   hipStream_t s = ctx->s();
+  // The persistent kernel takes the batch when its problems share the sweep
+  // mode and the Laplacian form (the kernel is compiled per mode); one block
+  // per compute unit then walks the tiles of all of them.
+  bool same = tc.pipe != 0;
+  for (int p = 1; p < m.nprob && same; ++p)
+    same = m.mode[p] == m.mode[0] && m.a[p].iso == m.a[0].iso;
+  if (same && tc.ex == 112 && tc.ez == 112 && tc.rz == 14 && tc.tmax == 8) {
+    const dim3 grid(unsigned(std::max(8, ctx->cus / 8 * 8)));
+    const int mode = m.mode[0];
+#define VIP_PIPE_MULTI(ISO)                                                                       \
+  if (mode == BMODE_FWD) fd_pipe<BMODE_FWD, 112, 112, 14, 8, ISO, true><<<grid, block, 0, s>>>(m);      \
+  else if (mode == BMODE_REC) fd_pipe<BMODE_REC, 112, 112, 14, 8, ISO, true><<<grid, block, 0, s>>>(m); \
+  else if (mode == BMODE_FWS) fd_pipe<BMODE_FWS, 112, 112, 14, 8, ISO, true><<<grid, block, 0, s>>>(m); \
+  else fd_pipe<BMODE_ADJ, 112, 112, 14, 8, ISO, true><<<grid, block, 0, s>>>(m);
+    if (m.a[0].iso) {
+      VIP_PIPE_MULTI(true)
+    } else {
+      VIP_PIPE_MULTI(false)
+    }
+#undef VIP_PIPE_MULTI
+    VIP_LAUNCH_CHECK();
+    return VIP_OK;
+  }
+  const dim3 grid(unsigned((acc + 7) / 8 * 8));
 #define VIP_MULTI_CASE(C, EX, EZ, RZ, TM)                            \
   if (cfg == C) {                                                    \
     fd_block_multi<EX, EZ, RZ, TM><<<grid, block, 0, s>>>(m);        \
@@ -649,7 +673,7 @@ static vip_status launch_multi(vip_ctx *ctx, int cfg,
   VIP_MULTI_CASE(3, 64, 64, 8, 4)
   VIP_MULTI_CASE(4, 128, 64, 8, 4)
   VIP_MULTI_CASE(5, 104, 104, 13, 6)
-  VIP_MULTI_CASE(6, 112, 112, 14, 8)   // the batched launch runs shape 6 one block per tile
+  VIP_MULTI_CASE(6, 112, 112, 14, 8)   // shape 6 with mixed sweep modes: one block per tile
 #undef VIP_MULTI_CASE
   return VIP_E_UNSUPPORTED;
 }

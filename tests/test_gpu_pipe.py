@@ -113,3 +113,33 @@ def test_pipe_bitwise_with_many_tiles_per_block():
             assert c.poll(c.workspace(tag, 0)) == 0
             c._ws.pop(tag, None)
     torch.cuda.empty_cache()
+
+
+def test_pipe_batch_of_uneven_problems_bitwise_equals_single_runs():
+    """Three problems of different grids, record lengths and shot counts in
+    one batched call with shape 6: launches whose problems share the sweep mode
+    run the persistent kernel over all their tiles (a block's run crosses from
+    one problem to the next), the others the one-block-per-tile batch kernel;
+    either way each problem's result is bitwise its single-problem result."""
+    c = ctx()
+    cases = [build_case(small_problem("u1", nx=70, nz=37, nt=181, ns=3, seed=11)),
+             build_case(small_problem("u2", nx=90, nz=50, nt=150, ns=2, seed=12)),
+             build_case(small_problem("u3", nx=120, nz=64, nt=201, ns=4, seed=13))]
+    probs = []
+    for case in cases:
+        grid, geom = grid_geom(c, case)
+        probs.append(vb.Problem(grid, geom, dev(case.particles), dev(case.dobs), case.sigma,
+                                lo=dev(case.lo), hi=dev(case.hi)))
+    c.set_tile(PIPE)
+    for k in (13, 50):
+        vb.vip_grad_logpost_multi(c, probs, ckpt_every=k)
+        torch.cuda.synchronize()
+        for j, p in enumerate(probs):
+            lp, g = vb.vip_grad_logpost(c, p.grid, p.geom, p.vel, p.dobs, p.sigma, ckpt_every=k,
+                                        lo=p.lo, hi=p.hi, ws_tag=f"pipe_single{j}")
+            same = torch.equal(lp, p.logpost) and torch.equal(g, p.grad)
+            print(f"pipe batch k={k} problem {j}: bitwise {same}", flush=True)
+            assert same, (k, j)
+    c.set_tile(-2)
+    for j in range(3):
+        c._ws.pop(f"pipe_single{j}", None)
