@@ -559,12 +559,11 @@ __global__ void bandwidth_kernel(const uint32_t *sel, long long count, int n, in
 }
 
 // ---- kernel matrix and row sums ---------------------------------------------
-// With khi non-null the row is also written as BF16 pairs k = hi + lo
-// (hi = bf16(k), lo = bf16(k - hi)) in rows of ldk, zero past column n.
+// With khi non-null the row is also written in BF16 (bf16(k), rounded to
+// nearest even) in rows of ldk, zero past column n.
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 __global__ __launch_bounds__(256) void rbf_kernel(const float *D, const double *h2, float *K,
-                                                  float *s, int n, uint16_t *khi, uint16_t *klo,
-                                                  int ldk) {
+                                                  float *s, int n, uint16_t *khi, int ldk) {
   __shared__ double part[4];
   const int i = blockIdx.x;
   const float inv = float(1.0 / (2.0 * h2[0]));
@@ -573,17 +572,10 @@ __global__ __launch_bounds__(256) void rbf_kernel(const float *D, const double *
     float k = expf(-D[(long long)i * n + j] * inv);
     K[(long long)i * n + j] = k;
     acc += double(k);
-    if (khi) {
-      const uint16_t h = f32_to_bf16_rne(k);
-      khi[(long long)i * ldk + j] = h;
-      klo[(long long)i * ldk + j] = f32_to_bf16_rne(k - bf16_to_f32(h));
-    }
+    if (khi) khi[(long long)i * ldk + j] = f32_to_bf16_rne(k);
   }
   if (khi)
-    for (int j = n + int(threadIdx.x); j < ldk; j += 256) {
-      khi[(long long)i * ldk + j] = 0;
-      klo[(long long)i * ldk + j] = 0;
-    }
+    for (int j = n + int(threadIdx.x); j < ldk; j += 256) khi[(long long)i * ldk + j] = 0;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -1194,11 +1186,14 @@ __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const 
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
-// The same update with the product K B on the BF16 matrix cores, each FP32
-// operand split into a BF16 pair x = hi + lo (hi = bf16(x), lo = bf16(x - hi))
-// and the product taken as hi hi + hi lo + lo hi.  The dropped lo lo term and
-// the rounding of lo stay below 2^-16 of each product, under the error the
-// BF16 Gram already puts into K; this is the update of the BF16 path.
+// The same update with the product K B on the BF16 matrix cores: K rounded to
+// BF16 (the precision its distances come from on this path), and the FP32 B
+// split into a BF16 pair B = hi + lo (hi = bf16(B), lo = bf16(B - hi)), the
+// product taken as K hi + K lo.  The rounding of K alone contributes about
+// 4e-5 relative L2 to phi at n = 2048 (an FP64 emulation on the c5 inputs
+// with the exact K: 2.4e-6 with K split as well, 1.6e-3 with B not split), a
+// fraction of what the BF16 Gram already puts into K through the distances;
+// this is the update of the BF16 path.
 //
 // bpair_kernel forms B = G Q^-1 - Xc / h^2 once (Xc = x - xbar recomputed, the
 // centring kernel does not store it on this path) and splits it.  Rows j and
@@ -1248,25 +1243,24 @@ __global__ __launch_bounds__(256) void bpair_kernel(const float *g, const float 
 
 // Block: 128 particles x 256 coordinates, 4 waves (2 x 2) of 2 x 4 tiles of
 // 32 x 32 (v_mfma_f32_32x32x16_bf16, operand and result layout as in the Gram
-// kernel), 60 KB of LDS and at most 256 registers, so that two blocks share a
+// kernel), 50 KB of LDS and at most 256 registers, so that two blocks share a
 // compute unit: one block's epilogue (HBM-bound) and barriers then overlap
 // the other's matrix instructions.  The particle index j runs in stages of
 // 32 through LDS, the next stage prefetched into registers.  A = K rows i (K
-// is symmetric) with 32 consecutive j from the split copy; a B fragment is
+// is symmetric) with 32 consecutive j from the BF16 copy; a B fragment is
 // the four 32-bit pairs of one column and group, stored as such by
 // bpair_kernel and kept column by column in LDS (16 pairs and 4 cells of
 // padding per column, so that the 16-byte accesses of 8 consecutive lanes
-// meet distinct banks).  The three products go over all eight tiles in turn,
+// meet distinct banks).  The two products go over all eight tiles in turn,
 // so that consecutive matrix instructions accumulate into different tiles.
 constexpr int VM = 128, VN = 256, VK = 32, VKP = VK + 8, VBT = VK / 2 + 4, VT = 256;
 template <bool RULE>
-__global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void update_bf16x3_kernel(
-    const uint16_t *khi, const uint16_t *klo, int ldk, const uint32_t *bph, const uint32_t *bpl,
+__global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void update_bf16x2_kernel(
+    const uint16_t *khi, int ldk, const uint32_t *bph, const uint32_t *bpl,
     long long dp, const float *xbar, const float *s, const double *h2, float *x, float *phi,
     const float *lo, const float *hi, int n, long long d, int mblocks, float eps, OptArgs opt,
     uint32_t *status) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[VM][VKP];   // Ah[i][k] = hi(K[i0 + i][j0 + k])
-  __shared__ __attribute__((aligned(16))) uint16_t Al[VM][VKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[VM][VKP];   // Ah[i][k] = bf16(K[i0 + i][j0 + k])
   __shared__ __attribute__((aligned(16))) uint32_t Bh[VN][VBT];   // Bh[a][p] = pair j0 / 2 + p
   __shared__ __attribute__((aligned(16))) uint32_t Bl[VN][VBT];
   const int per = int(gridDim.x) >> 3;
@@ -1281,18 +1275,15 @@ __global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   // staging: A row t / 2, k half 16 (t % 2); B column t, all four groups
   const int ar = t >> 1, ak = (t & 1) * 16;
   const bool bin = a0 + t < dp;   // dp is a multiple of 8: zero columns beyond it
-  uint4 pah[2], pal[2], pbh[4], pbl[4];
+  uint4 pah[2], pbh[4], pbl[4];
   auto load_stage = [&](int j0) {
     const int i = i0 + ar;
     if (i < n) {
       const uint16_t *ph = khi + (long long)i * ldk + j0 + ak;
-      const uint16_t *pl = klo + (long long)i * ldk + j0 + ak;
       pah[0] = *reinterpret_cast<const uint4 *>(ph);
       pah[1] = *reinterpret_cast<const uint4 *>(ph + 8);
-      pal[0] = *reinterpret_cast<const uint4 *>(pl);
-      pal[1] = *reinterpret_cast<const uint4 *>(pl + 8);
     } else {
-      pah[0] = pah[1] = pal[0] = pal[1] = make_uint4(0, 0, 0, 0);
+      pah[0] = pah[1] = make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -1304,8 +1295,6 @@ __global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   auto store_stage = [&]() {
     *reinterpret_cast<uint4 *>(&Ah[ar][ak]) = pah[0];
     *reinterpret_cast<uint4 *>(&Ah[ar][ak + 8]) = pah[1];
-    *reinterpret_cast<uint4 *>(&Al[ar][ak]) = pal[0];
-    *reinterpret_cast<uint4 *>(&Al[ar][ak + 8]) = pal[1];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       *reinterpret_cast<uint4 *>(&Bh[t][4 * h]) = pbh[h];
@@ -1326,13 +1315,11 @@ __global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
     for (int kk = 0; kk < VK; kk += 16) {
       const int kq = kk + 8 * (lane >> 5);   // first of my 8 k
-      bf16x8_t fah[2], fal[2], fbh[4], fbl[4];
+      bf16x8_t fah[2], fbh[4], fbl[4];
       for (int m = 0; m < 2; ++m) {
         const int row = wi * 64 + m * 32 + (lane & 31);
         const uint4 rh = *reinterpret_cast<const uint4 *>(&Ah[row][kq]);
-        const uint4 rl = *reinterpret_cast<const uint4 *>(&Al[row][kq]);
         __builtin_memcpy(&fah[m], &rh, 16);
-        __builtin_memcpy(&fal[m], &rl, 16);
       }
       for (int q = 0; q < 4; ++q) {
         const int col = wj * 128 + q * 32 + (lane & 31);
@@ -1341,9 +1328,6 @@ __global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         __builtin_memcpy(&fbh[q], &uh, 16);
         __builtin_memcpy(&fbl[q], &ul, 16);
       }
-      for (int m = 0; m < 2; ++m)
-        for (int q = 0; q < 4; ++q)
-          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[m], fbh[q], acc[m][q], 0, 0, 0);
       for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 4; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbl[q], acc[m][q], 0, 0, 0);
@@ -1553,7 +1537,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   bandwidth_kernel<<<dim3(1), dim3(1), 0, s>>>(P.sel, count, n, bw_mode, h_fixed, P.h2, h2_out);
   VIP_LAUNCH_CHECK();
   rbf_kernel<<<dim3(n), dim3(256), 0, s>>>(P.D, P.h2, P.K, P.s, n,
-                                           split_update ? P.khi : nullptr, P.klo, P.ldk);
+                                           split_update ? P.khi : nullptr, P.ldk);
   VIP_LAUNCH_CHECK();
 
   // phi and x + eps phi (or a step rule); with noise the prior clip waits for
@@ -1572,9 +1556,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     VIP_LAUNCH_CHECK();
     const int vblocks = (n + VM - 1) / VM;
     const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
-    auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x3_kernel<false> : update_bf16x3_kernel<true>;
+    auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x2_kernel<false> : update_bf16x2_kernel<true>;
     kern<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
-        P.khi, P.klo, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, ulo, uhi, n, d,
+        P.khi, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, ulo, uhi, n, d,
         vblocks, float(eps), oa, P.status);
   } else {
     auto *kern = oa.kind == VIP_OPT_SGD ? update_mfma_kernel<false> : update_mfma_kernel<true>;

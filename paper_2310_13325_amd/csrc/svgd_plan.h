@@ -19,7 +19,7 @@ struct SvgdPlan {
   double *h2 = nullptr, *L = nullptr;
   float *Lf = nullptr;   // FP32 copy of L, transposed (Lf[j][i] = L[i][j])
   float *xi = nullptr, *phi = nullptr;
-  uint16_t *khi = nullptr, *klo = nullptr;   // K split into BF16 pairs, rows of ldk
+  uint16_t *khi = nullptr;                   // K in BF16, rows of ldk
   uint32_t *bph = nullptr, *bpl = nullptr;   // B split: pairs of rows, 4 pairs of a column together
   int ldk = 0;
   long long dp = 0;
@@ -83,7 +83,6 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->phi = A.take<float>(nd);
   P->ldk = (n + 31) / 32 * 32;
   P->khi = A.take<uint16_t>(size_t(n) * size_t(P->ldk));
-  P->klo = A.take<uint16_t>(size_t(n) * size_t(P->ldk));
   P->dp = (d + 7) / 8 * 8;
   P->bph = A.take<uint32_t>(size_t(P->ldk / 2) * size_t(P->dp));
   P->bpl = A.take<uint32_t>(size_t(P->ldk / 2) * size_t(P->dp));
