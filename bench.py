@@ -714,11 +714,12 @@ def main():
         # Matrix-core work of one BF16-path step against the dense BF16 peak,
         # two ways: algorithmic -- the upper Gram (the 136 upper 128 x 128
         # blocks of 256, 2 n^2 d x 136/256) and one product K B (2 n^2 d); and
-        # executed -- the split update runs that product as three BF16 products
+        # executed -- the update runs that product as two BF16 products (K
+        # times the two halves of the split B)
         nn_d = 2.0 * case.n * case.n * case.d
         nb = (case.n + 127) // 128
         gram = nn_d * (nb * (nb + 1) / 2) / nb ** 2
-        alg, executed = gram + nn_d, gram + 3.0 * nn_d
+        alg, executed = gram + nn_d, gram + 2.0 * nn_d
         rate = svgd["bf16_gram"]
         svgd["bf16_path_matrix_core"] = {
             "algorithmic_flops_per_step": alg, "algorithmic_TFLOPs": round(alg * rate / 1e12, 1),
