@@ -61,9 +61,10 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
     if constexpr (MULTI) return kp->start[kp->nprob];
     else return kp->total_tiles;
   };
-  auto prob_of = [](KParams *kp, int tt) -> int {
+  // (tiles only move forward, so the search starts at a known problem p0 <= the answer)
+  auto prob_of = [](KParams *kp, int tt, int p0) -> int {
     if constexpr (MULTI) {
-      int p = 0;
+      int p = p0;
       while (p + 1 < kp->nprob && tt >= kp->start[p + 1]) ++p;
       return p;
     } else {
@@ -106,9 +107,8 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   int t = xbeg + (int(blockIdx.x) >> 3);
   if (t >= tend) return;
 
-  const int col = int(threadIdx.x) % EX;
-  const int strip = int(threadIdx.x) / EX;
-  const int zl0 = strip * RZ;              // first extended-tile row of my strip
+  int col = int(threadIdx.x) % EX;
+  int zl0 = (int(threadIdx.x) / EX) * RZ;  // first extended-tile row of my strip
 
   // once per block: zero the padding cells of both u buffers (every other cell
   // is written before it is read); wavelet samples of this launch's steps
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   float av[ADJ ? RZ : 1];
   int pb = 0;   // the LDS u buffer the next tile's u is published into
   {
-    const int p0 = prob_of(kp0, t);
+    const int p0 = prob_of(kp0, t, 0);
     KArgs &a0 = args_of(kp0, p0);
     const int lt0 = t - first_of(kp0, p0);
     stage_u(a0, lt0);
@@ -203,7 +203,9 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   for (;;) {
     KParams *kp = kp0;
     asm volatile("" : "+s"(kp));
-    const int prob = prob_of(kp, t);
+    int tid = int(threadIdx.x);
+    if constexpr (MULTI) asm volatile("" : "+v"(col), "+v"(zl0), "+v"(tid));
+    const int prob = prob_of(kp, t, cur_p < 0 ? 0 : cur_p);
     KArgs &a = args_of(kp, prob);
     const int lt = t - first_of(kp, prob);
     const int NX = a.NX, NZ = a.NZ;
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
       for (int r = 0; r < RZ; ++r) q[r] = PREQ ? qn[r] : av[r];
     }
 #pragma unroll
-    for (int r = 0; r < RZ; ++r) u[r] = a.zero_in ? 0.0f : stage[r][threadIdx.x];
+    for (int r = 0; r < RZ; ++r) u[r] = a.zero_in ? 0.0f : stage[r][tid];
     if (ADJ) {
 #pragma unroll
       for (int r = 0; r < RZ; ++r) acc[r] = 0.0f;
@@ -255,15 +257,15 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
       // every thread is done with the previous tile's row tables (on the
       // first tile, the padding of the u buffers is being zeroed)
       if (!first) __syncthreads();
-      for (int e = threadIdx.x; e < EZ; e += NTHREADS) {
+      for (int e = tid; e < EZ; e += NTHREADS) {
         const int Z = Z0 + e;
         const bool zin = Z >= 0 && Z < NZ;
         gzs[e] = zin ? a.gz[Z] : 0.0f;
         rrs[e] = (zin && MODE != BMODE_REC) ? a.rrow[Z] : -1;   // receivers: traces or residual
       }
       // wavelet samples of this launch's steps (forward, recompute)
-      if (!ADJ && newprob && int(threadIdx.x) < a.steps)
-        injs[threadIdx.x] = a.wavelet[a.n_start + int(threadIdx.x)] * a.inv_area;
+      if (!ADJ && newprob && tid < a.steps)
+        injs[tid] = a.wavelet[a.n_start + tid] * a.inv_area;
       __syncthreads();
       cur_p = prob;
       cur_pos = pos;
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
     // the next tile's loads fly while this tile steps (my staging words are
     // free: their values are in u)
     if (more) {
-      const int pn = prob_of(kp, tnext);
+      const int pn = prob_of(kp, tnext, prob);
       KArgs &an = args_of(kp, pn);
       const int ltn = tnext - first_of(kp, pn);
       stage_u(an, ltn);
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
       // (the next tile's problem is looked up again rather than kept live
       // across the steps)
       KParams *kq = kp;
-      const int pn = prob_of(kq, tnext);
+      const int pn = prob_of(kq, tnext, prob);
       KArgs &an = args_of(kq, pn);
       const int ltn = tnext - first_of(kq, pn);
       if (pn != prob || tile_particle(an, ltn) != particle || tile_pos(an, ltn) != pos)
@@ -443,20 +445,34 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
     // write back the owned interior: u, q and (adjoint) the launch's imaging
     // partial into the FP64 sum (one add per point and launch, so the
     // no-return atomic adds what a read, add and store would)
+    // (the bases of my pair's fields are formed once, as values the compiler
+    // cannot recompute from the arguments: otherwise it reloads the arguments
+    // and redoes the 64-bit arithmetic for every row)
+    // grid index of my first row: an owned point is on the grid, so off0 is 4
+    // times that index taken modulo 2^32; the row may lie above the grid (a
+    // negative index), hence the signed division
+    const int i0 = int(off0) / 4;
+    if (a.u_out) {
+      typedef __attribute__((address_space(1))) float GFloat;
+      GFloat *uo = (GFloat *)(a.u_out + lp * a.out_stride);
+      GFloat *qo = (GFloat *)(a.q_out + lp * a.out_stride);
+      asm volatile("" : "+s"(uo), "+s"(qo));
 #pragma unroll
-    for (int r = 0; r < RZ; ++r) {
-      if (!((own >> r) & 1u)) continue;
-      // grid index of row r: an owned point is on the grid, so off0 is 4 times
-      // the index of my first row taken modulo 2^32; that row may lie above
-      // the grid (a negative index), hence the signed division
-      const int i = int(off0) / 4 + r * NX;
-      if (a.u_out) {
-        a.u_out[lp * a.out_stride + i] = u[r];
-        a.q_out[lp * a.out_stride + i] = q[r];
+      for (int r = 0; r < RZ; ++r) {
+        if (!((own >> r) & 1u)) continue;
+        uo[i0 + r * NX] = u[r];
+        qo[i0 + r * NX] = q[r];
       }
-      if (ADJ)
-        __hip_atomic_fetch_add(a.acc64 + lp * a.acc64_stride + i, double(acc[r]), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (ADJ) {
+      typedef __attribute__((address_space(1))) double GDouble;
+      GDouble *ao = (GDouble *)(a.acc64 + lp * a.acc64_stride);
+      asm volatile("" : "+s"(ao));
+#pragma unroll
+      for (int r = 0; r < RZ; ++r)
+        if ((own >> r) & 1u)
+          __hip_atomic_fetch_add(ao + i0 + r * NX, double(acc[r]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!more) break;
     t = tnext;

@@ -622,6 +622,12 @@ static vip_status launch_block(vip_ctx *ctx, int mode, int cfg, int npairs, Bloc
 
 static vip_status launch_multi(vip_ctx *ctx, int cfg,
                                const std::vector<const std::pair<int, BlockArgs> *> &items) {
+  // a merged launch left with one problem (the others have finished their
+  // sweeps) takes that problem's own kernel, which skips the per-tile lookup
+  if (items.size() == 1) {
+    BlockArgs a = items[0]->second;
+    return launch_block(ctx, items[0]->first, cfg, a.total_tiles / a.tiles_per_pair, a);
+  }
   MultiArgs m;
   std::memset(&m, 0, sizeof(m));
   m.nprob = int(items.size());
