@@ -78,6 +78,8 @@ struct BlockArgs {
   float inv_area;
   const float *gx, *gz, *c;
   const int *src_idx, *rrow, *rmap;
+  int nb;                 // sponge width (gx, gz: one profile of depth into the sponge)
+  int nrows;              // distinct receiver rows (rows of rmap)
   const float *wavelet;
   int zero_in;
   const float *u_in, *q_in;

@@ -16,15 +16,18 @@
 //  * q of tile i+1 goes into registers where the mode leaves room (forward,
 //    forward-with-store, recompute); the adjoint, whose imaging sum and a^n
 //    prefetch fill its registers, loads it once tile i is written back;
-//  * c of tile i+1 is usually that of tile i: a block's run is ordered with
-//    the pairs fastest at each tile position, and the pairs of one particle
-//    (its shots) are consecutive, so c is reloaded only when the particle or
-//    the position changes.
+//  * c of tile i+1 is reloaded only when the particle or the position
+//    changes;
+//  * what the set-up of a tile needs besides the fields (the sponge factors,
+//    which receivers lie in a thread's rows) comes from small per-problem LDS
+//    tables filled once per block and problem, so that a tile starts without a
+//    barrier or a dependent memory round trip of its own.
 //
-// Each XCD takes a contiguous range of tiles and each of its blocks a
-// contiguous run of that range.  The grid is one block per compute unit (the
-// LDS of one block exceeds half a unit's), so every block is resident from the
-// start.
+// Each XCD takes a contiguous range of tiles; its blocks step through that
+// range J tiles apart (J blocks per XCD), so that the blocks of an XCD work on
+// neighbouring tiles at the same time and share their halos in its L2.  The
+// grid is one block per compute unit (the LDS of one block exceeds half a
+// unit's), so every block is resident from the start.
 #pragma once
 
 #include <type_traits>
@@ -33,10 +36,20 @@
 
 namespace vip {
 
+// Per-problem LDS tables of the persistent kernel: the sponge profile g(d) at
+// depth d = 0 .. nb into the sponge (gx and gz are the same profile), the grid
+// row of each receiver row and the receiver id of each (receiver row, column).
+// A problem whose sponge or receiver rows exceed them takes the sponge factors
+// and receiver ids from global memory instead.
+constexpr int kPipeProf = 64;     // sponge widths nb < 64
+constexpr int kPipeRows = 8;      // receiver rows
+constexpr int kPipeRmap = 1400;   // receiver rows x NX
+
 // LDS of one persistent block.
 template <int EX, int EZ, int RZ, int TMAX>
 constexpr int pipe_lds_bytes() {
-  return 2 * (EZ + 4) * (EX + 4) * 4 + RZ * EX * (EZ / RZ) * 4 + 8 * EZ + 4 * TMAX;
+  return 2 * (EZ + 4) * (EX + 4) * 4 + RZ * EX * (EZ / RZ) * 4 + 4 * TMAX +
+         4 * (kPipeProf + kPipeRows + kPipeRmap);
 }
 
 // MULTI: the launch carries several problems (MultiArgs: tile ranges
@@ -92,9 +105,10 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   static_assert(pipe_lds_bytes<EX, EZ, RZ, TMAX>() <= kLdsBytes, "LDS");
   __shared__ float lds[2][EZ + 4][LW];
   __shared__ float stage[RZ][NTHREADS];   // u of the next tile: row r of thread t at [r][t]
-  __shared__ float gzs[EZ];     // z damping of each extended-tile row (0 outside the grid)
-  __shared__ int rrs[EZ];       // receiver-row index of each extended-tile row (-1: none)
   __shared__ float injs[TMAX];  // forward / recompute: source term w(t_n)/(dx dz) of each step
+  __shared__ float prof[kPipeProf];   // sponge factor at depth d into the sponge
+  __shared__ int rowz[kPipeRows];     // grid row of receiver row k
+  __shared__ int rmapl[kPipeRmap];    // receiver id at (receiver row k, column X), -1: none
 
   // This block's run of tiles: XCD x = blockIdx % 8 owns [x per, (x + 1) per),
   // its j-th block the j-th of J runs of that range.  Tile index t stands for
@@ -253,43 +267,82 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
       const int sz = sidx / NX, sx = sidx - (sidx / NX) * NX;
       if (sx == X && sz >= Z0 + zl0 && sz < Z0 + zl0 + RZ) src_r = sz - (Z0 + zl0);
     }
-    if (newpos) {
-      // every thread is done with the previous tile's row tables (on the
-      // first tile, the padding of the u buffers is being zeroed)
+    if (newprob) {
+      // this problem's tables (every thread is done with the last problem's;
+      // on the first tile the padding of the u buffers is being zeroed)
       if (!first) __syncthreads();
-      for (int e = tid; e < EZ; e += NTHREADS) {
-        const int Z = Z0 + e;
-        const bool zin = Z >= 0 && Z < NZ;
-        gzs[e] = zin ? a.gz[Z] : 0.0f;
-        rrs[e] = (zin && MODE != BMODE_REC) ? a.rrow[Z] : -1;   // receivers: traces or residual
+      const int nrows = a.nrows;
+      for (int d = tid; d <= a.nb && d < kPipeProf; d += NTHREADS) prof[d] = a.gz[a.nb - d];
+      for (int Z = tid; Z < NZ; Z += NTHREADS) {
+        const int rr = a.rrow[Z];
+        if (rr >= 0 && rr < kPipeRows) rowz[rr] = Z;
       }
+      if (nrows <= kPipeRows && nrows * NX <= kPipeRmap)
+        for (int e = tid; e < nrows * NX; e += NTHREADS) rmapl[e] = a.rmap[e];
       // wavelet samples of this launch's steps (forward, recompute)
-      if (!ADJ && newprob && tid < a.steps)
-        injs[tid] = a.wavelet[a.n_start + tid] * a.inv_area;
+      if (!ADJ && tid < a.steps) injs[tid] = a.wavelet[a.n_start + tid] * a.inv_area;
       __syncthreads();
+    }
+    if (newpos) {
       cur_p = prob;
       cur_pos = pos;
-      const float gxv = xin ? a.gx[X] : 0.0f;
+      // sponge factors g = gz gx of my rows: depth into the sponge, as the
+      // profile is tabulated (0 off the grid)
+      const int nb = a.nb;
+      const bool tab = nb < kPipeProf;
+      const int dx = max(max(nb - X, X - (NX - 1 - nb)), 0);
+      const float gxv = xin ? (tab ? prof[dx] : a.gx[X]) : 0.0f;
 #pragma unroll
-      for (int r = 0; r < RZ; ++r) gr[r] = gzs[zl0 + r] * gxv;
+      for (int r = 0; r < RZ; ++r) {
+        const int Z = Z0 + zl0 + r;
+        const int dz = max(max(nb - Z, Z - (NZ - 1 - nb)), 0);
+        const float gzv = (Z >= 0 && Z < NZ) ? (tab ? prof[dz] : a.gz[Z]) : 0.0f;
+        gr[r] = gzv * gxv;
+      }
+      // receivers in my rows and column: the first in registers, any further
+      // ones as a row mask (their ids are looked up per step)
       rec_r0 = -1;
       rec_id0 = 0;
       rec_rest = 0;
       if (MODE != BMODE_REC && xin) {
-#pragma unroll
-        for (int r = 0; r < RZ; ++r) {
-          const int rr = rrs[zl0 + r];
-          if (rr >= 0) {
-            const int rid = a.rmap[rr * NX + X];
-            if (rid >= 0) {
-              if (rec_r0 < 0) {
-                rec_r0 = r;
-                rec_id0 = rid;
-              } else {
-                rec_rest |= 1u << r;
+        uint32_t mask = 0;
+        int best = RZ, best_id = 0;
+        const int nrows = a.nrows;
+        if (nrows <= kPipeRows && nrows * NX <= kPipeRmap) {
+          for (int k = 0; k < nrows; ++k) {
+            const int r = rowz[k] - (Z0 + zl0);
+            if (r >= 0 && r < RZ) {
+              const int rid = rmapl[k * NX + X];
+              if (rid >= 0) {
+                mask |= 1u << r;
+                if (r < best) {
+                  best = r;
+                  best_id = rid;
+                }
               }
             }
           }
+        } else {
+#pragma unroll
+          for (int r = 0; r < RZ; ++r) {
+            const int Z = Z0 + zl0 + r;
+            const int rr = (Z >= 0 && Z < NZ) ? a.rrow[Z] : -1;
+            if (rr >= 0) {
+              const int rid = a.rmap[rr * NX + X];
+              if (rid >= 0) {
+                mask |= 1u << r;
+                if (r < best) {
+                  best = r;
+                  best_id = rid;
+                }
+              }
+            }
+          }
+        }
+        if (mask) {
+          rec_r0 = best;
+          rec_id0 = best_id;
+          rec_rest = mask & ~(1u << best);
         }
       }
     }
@@ -348,7 +401,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
 #pragma unroll
           for (int r = 0; r < RZ; ++r) {
             if ((rec_rest >> r) & 1u) {
-              const int rid = a.rmap[rrs[zl0 + r] * NX + X];
+              const int rid = a.rmap[a.rrow[Z0 + zl0 + r] * NX + X];
               const float rho = a.rho[lp * a.rho_stride + (long long)(n + 1) * a.nr + rid];
               q[r] = fmaf(cc[r], rho, q[r]);
             }
@@ -407,7 +460,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
 #pragma unroll
           for (int r = 0; r < RZ; ++r) {
             if (((rec_rest & own) >> r) & 1u) {
-              const int rid = a.rmap[rrs[zl0 + r] * NX + X];
+              const int rid = a.rmap[a.rrow[Z0 + zl0 + r] * NX + X];
               d[(long long)(n + 1) * a.nr + rid] = u[r];
               if (n == 0) d[rid] = 0.0f;
             }

@@ -726,6 +726,8 @@ static BlockArgs block_args(const FwiDims &D, const FwiPlan &P, const float *wav
   a.src_idx = P.src;
   a.rrow = P.rrow;
   a.rmap = P.rmap;
+  a.nb = D.nb;
+  a.nrows = D.nrows;
   a.wavelet = wavelet;
   return a;
 }

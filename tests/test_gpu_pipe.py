@@ -143,3 +143,74 @@ def test_pipe_batch_of_uneven_problems_bitwise_equals_single_runs():
     c.set_tile(-2)
     for j in range(3):
         c._ws.pop(f"pipe_single{j}", None)
+
+
+def _layout_case(kind):
+    """Receiver and sponge layouts that take each path of the persistent
+    kernel's tile set-up: receivers on three rows sharing columns (the LDS
+    receiver tables, with several receivers of one column in one strip), a
+    borehole line of 11 rows plus other rows (more receiver rows than the LDS
+    tables hold: ids from global memory), and a 64-cell sponge (wider than the
+    LDS profile: sponge factors from global memory)."""
+    if kind == "wide_sponge":
+        prob = configs.Problem("wide_sponge", nx=40, nz=30, dx=10.0, nt=121, dt=1e-3, ns=2, np=3,
+                               f0=18.0, src_iz=1, rec_iz=2, model="layers_anomalies",
+                               prior="rowmean_pm500", noise="rms_1pct", seed=21, nb=64)
+        case = build_case(prob)
+        return prob, case, case.ogeom
+    prob = small_problem(nt=151, ns=3)
+    case = build_case(prob)
+    nx, nz = prob.nx, prob.nz
+    src = [(0, 3), (nz // 2, nx - 2), (nz - 1, nx // 2)]
+    if kind == "rows3":
+        rec = [(z, x) for z in (2, 5, 9) for x in range(4, nx - 4, 3)] + [(nz - 1, 7)]
+    else:
+        rec = ([(r, 40) for r in range(2, 13)] + [(r, 0) for r in range(20, 30)] +
+               [(2, 5), (2, 6), (nz - 1, nx - 1)])
+    og = ofwi.Geometry(src_iz=tuple(s[0] for s in src), src_ix=tuple(s[1] for s in src),
+                       rec_iz=tuple(r[0] for r in rec), rec_ix=tuple(r[1] for r in rec), f0=prob.f0)
+    return prob, case, og
+
+
+@pytest.mark.parametrize("kind", ["rows3", "many_rows", "wide_sponge"])
+def test_pipe_bitwise_across_receiver_and_sponge_layouts(kind):
+    _same_shape()
+    prob, case, og = _layout_case(kind)
+    nrows = len(set(og.rec_iz))
+    two_in_strip = kind != "wide_sponge"
+    print(f"layout {kind}: {nrows} receiver rows, sponge {prob.nb}", flush=True)
+    clean = ofwi.simulate(case.v_true, case.ogrid, og)
+    sigma = 0.01 * float(np.sqrt(np.mean(clean ** 2)))
+    dobs = (clean + sigma * np.random.default_rng(5).standard_normal(clean.shape)).astype(np.float32)
+    c = ctx()
+    grid = vb.Grid(nx=prob.nx, nz=prob.nz, nt=prob.nt, dx=prob.dx, dt=prob.dt, vmax=case.vmax,
+                   nb=prob.nb, sponge_alpha=prob.alpha)
+    w = vb.vip_ricker(c, prob.nt, prob.dt, prob.f0)
+    geom = vb.Geometry(og.src_iz, og.src_ix, og.rec_iz, og.rec_ix, w)
+    x = dev(case.particles)
+    outs = {}
+    for tile in (BLOCK, PIPE):
+        c.set_tile(tile)
+        outs[tile] = vb.vip_forward(c, grid, geom, x).cpu()
+    c.set_tile(-2)
+    assert torch.equal(outs[PIPE], outs[BLOCK]), kind
+    args = (c, grid, geom, x, dev(dobs), sigma)
+    lo, hi = dev(case.lo), dev(case.hi)
+    for kw in (dict(ckpt_every=13), dict(ckpt_every=50, stored_steps=prob.nt - 1)):
+        a = _grad(c, BLOCK, args, lo=lo, hi=hi, ws_tag="pipe_l0", **kw)
+        b = _grad(c, PIPE, args, lo=lo, hi=hi, ws_tag="pipe_l6", **kw)
+        same = torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        print(f"layout {kind} {kw}: bitwise {same}", flush=True)
+        assert same, (kind, kw)
+    lp_ref, g_ref = ofwi.grad_logpost(case.particles, case.ogrid, og, dobs, sigma, case.lo, case.hi)
+    for p in range(g_ref.shape[0]):
+        ew = rel(outs[PIPE][p].numpy(), ofwi.simulate(case.particles[p], case.ogrid, og))
+        eg = rel(b[1][p].numpy(), g_ref[p])
+        print(f"layout {kind} particle {p}: data {ew:.2e}, grad {eg:.2e}", flush=True)
+        assert ew <= 1e-5 and eg <= 1e-4
+    if two_in_strip:
+        # (the host-side count of strips holding two receivers of one column)
+        from tests.test_gpu_fwi import _strips_with_two_receivers
+        assert _strips_with_two_receivers(PIPE, prob, og) > 0
+    for tag in ("pipe_l0", "pipe_l6"):
+        c._ws.pop(tag, None)
