@@ -97,6 +97,32 @@ def traffic_from_counters(configuration: dict):
     return c
 
 
+def stream_rates(torch, mib=1024, reps=5):
+    """What plain streaming kernels (torch's fill, copy and a + b) reach on this
+    GPU, in GB/s of algorithmic bytes: a practical ceiling beside the published
+    HBM peak."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("fill", lambda: c.fill_(2.0), 4 * n),
+                             ("copy", lambda: c.copy_(a), 8 * n),
+                             ("add", lambda: torch.add(a, b, out=c), 12 * n)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def setup(prob, ctx, vb, synth, torch, npart):
     import numpy as np
     v, vbg = synth.true_model(prob)
@@ -581,6 +607,8 @@ def main():
                                "per point-step",
                 # counter-measured HBM bytes per launch over the live launch time
                 "measured_GBps": meas,
+                # plain streaming kernels on the same GPU, for scale
+                "stream_reference_GBps": stream_rates(torch),
                 "measured_frac": None if meas is None else round(meas / HBM_PEAK_GBS, 4),
                 "kernel": f"{kname}, {dom} mode", "modes": kinds,
                 # VALU issue rate from the counted wave instructions (SQ_INSTS_VALU)

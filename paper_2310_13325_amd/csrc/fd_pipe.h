@@ -105,7 +105,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   static_assert(pipe_lds_bytes<EX, EZ, RZ, TMAX>() <= kLdsBytes, "LDS");
   __shared__ float lds[2][EZ + 4][LW];
   __shared__ float stage[RZ][NTHREADS];   // u of the next tile: row r of thread t at [r][t]
-  __shared__ float injs[TMAX];  // forward / recompute: source term w(t_n)/(dx dz) of each step
+  __shared__ float injs[TMAX];  // source term w(t_n)/(dx dz) of each step of the launch
   __shared__ float prof[kPipeProf];   // sponge factor at depth d into the sponge
   __shared__ int rowz[kPipeRows];     // grid row of receiver row k
   __shared__ int rmapl[kPipeRmap];    // receiver id at (receiver row k, column X), -1: none
@@ -279,8 +279,9 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
       }
       if (nrows <= kPipeRows && nrows * NX <= kPipeRmap)
         for (int e = tid; e < nrows * NX; e += NTHREADS) rmapl[e] = a.rmap[e];
-      // wavelet samples of this launch's steps (forward, recompute)
-      if (!ADJ && tid < a.steps) injs[tid] = a.wavelet[a.n_start + tid] * a.inv_area;
+      // wavelet samples of this launch's steps (the adjoint's for its imaging
+      // term: a load of its own there would wait for the step's a^n loads)
+      if (tid < a.steps) injs[tid] = a.wavelet[ADJ ? a.n_start - tid : a.n_start + tid] * a.inv_area;
       __syncthreads();
     }
     if (newpos) {
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
       }
       if (ADJ) {
         if (src_r >= 0 && ((own >> src_r) & 1u)) {
-          const float f = a.wavelet[n] * a.inv_area;
+          const float f = injs[s];
 #pragma unroll
           for (int r = 0; r < RZ; ++r)
             if (r == src_r) acc[r] = fmaf(u[r], f, acc[r]);
