@@ -1427,6 +1427,231 @@ __global__ __launch_bounds__(VT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
+// The same update with the operands streamed through a ring of three LDS
+// stages by 16-byte loads that write LDS directly (no registers held while
+// they fly), two stages ahead of the matrix instructions.  Block: 256
+// particles x 256 coordinates, 8 waves (4 x 2) of 64 x 128 (2 x 4 tiles of
+// 32 x 32, the same fragments and the same order of matrix instructions per
+// tile as update_bf16x2_kernel, so phi is bitwise the same), one block per
+// compute unit (147 KB of LDS), two waves per SIMD.  A stage is 32 j:
+//  * A: rows i0 .. i0 + 255 of K in BF16, 64 bytes a row in four 16-byte
+//    chunks; chunk c of row r sits in slot c ^ ((r >> 2) & 3) of the row, so
+//    that the fragment reads of 16 consecutive rows meet distinct banks;
+//  * B: for each of the four groups of 8 j and each of the 256 columns, the
+//    16-byte pair words of bpair_kernel, hi and lo in two arrays.
+// Rows past n, and columns past dp, read as zeros (the loads' range check and
+// an offset beyond it).  The loads are written as inline assembly: a compiler
+// that sees loads writing LDS waits for them before any LDS access it cannot
+// prove disjoint, which would drain the ring at every stage; here the waits
+// are explicit (each wave issues 6 loads a stage, so waiting for all but the
+// newest 6 completes the stage to be read) and a barrier then makes every
+// wave's loads visible to all.
+constexpr int RM = 256, RN = 256, RK = 32, RS = 3, RT = 512;
+constexpr bool kUpdateRing = true;
+constexpr int R_A = RM * RK * 2, R_B = 4 * RN * 16, R_STAGE = R_A + 2 * R_B;
+template <bool RULE>
+__global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(2, 2))) void update_bf16x2_ring_kernel(
+    const uint16_t *khi, int ldk, const uint32_t *bph, const uint32_t *bpl,
+    long long dp, const float *xbar, const float *s, const double *h2, float *x, float *phi,
+    const float *lo, const float *hi, int n, long long d, int mblocks, float eps, OptArgs opt,
+    uint32_t *status) {
+  __shared__ __attribute__((aligned(16))) unsigned char ring[RS][R_STAGE];
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  const int nt = mblocks * int((d + RN - 1) / RN);
+  if (tb >= nt) return;
+  const int i0 = (tb % mblocks) * RM;
+  const long long a0 = (long long)(tb / mblocks) * RN;
+  // (the wave index as a scalar: the LDS addresses of the loads derive from it)
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wi = w >> 1, wj = w & 1;
+
+  // descriptors of K (rows past n out of range) and of the B pairs
+  typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+  auto rsrc = [](const void *base, uint32_t bytes) {
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    U32x4 r;
+    r.x = __builtin_amdgcn_readfirstlane(uint32_t(b));
+    r.y = __builtin_amdgcn_readfirstlane(uint32_t(b >> 32)) & 0xffffu;
+    r.z = __builtin_amdgcn_readfirstlane(bytes);
+    r.w = 0x00020000u;
+    return r;
+  };
+  const U32x4 rk = rsrc(khi, uint32_t(n) * uint32_t(ldk) * 2u);
+  const uint32_t bbytes = uint32_t(ldk / 2) * uint32_t(dp) * 4u;
+  const U32x4 rbh = rsrc(bph, bbytes), rbl = rsrc(bpl, bbytes);
+  const uint32_t ring0 = uint32_t(reinterpret_cast<uintptr_t>(
+      (__attribute__((address_space(3))) unsigned char *)&ring[0][0]));
+  // My six loads of a stage: numbers w + 8 k of the stage's 48 (16 of A,
+  // 16 of B hi, 16 of B lo), each 64 lanes x 16 bytes.
+  //   A load q (0..15): rows 16 q + lane / 4, chunk (lane % 4) ^ ((row >> 2) & 3)
+  //   B load q (0..15): group q / 4, columns 64 (q % 4) + lane
+  auto issue = [&](int st) {
+    const int j0 = st * RK;
+    const uint32_t base = ring0 + uint32_t((st % RS) * R_STAGE);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int q = (w + 8 * k) & 15;
+      uint32_t m0, off;
+      U32x4 r;
+      if (k < 2) {
+        const int row = 16 * q + (lane >> 2);
+        const int chunk = (lane & 3) ^ ((row >> 2) & 3);
+        m0 = base + uint32_t(q * 16 * 64);
+        off = (uint32_t(i0 + row) * uint32_t(ldk) + uint32_t(j0)) * 2u + uint32_t(chunk) * 16u;
+        if (i0 + row >= n) off = 0x80000000u;
+        r = rk;
+      } else {
+        const int h = q >> 2;
+        const long long a = a0 + 64 * (q & 3) + lane;
+        m0 = base + uint32_t(R_A + (k >= 4 ? R_B : 0) + (h * RN + 64 * (q & 3)) * 16);
+        off = a < dp ? uint32_t(((long long)(j0 / 8 + h) * dp + a) * 16) : 0x80000000u;
+        r = k >= 4 ? rbl : rbh;
+      }
+      uint32_t keep;
+      asm volatile(
+          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+          "buffer_load_dwordx4 %2, %3, 0 offen lds\n\ts_mov_b32 m0, %0"
+          : "=&s"(keep)
+          : "s"(m0), "v"(off), "s"(r)
+          : "memory");
+    }
+  };
+
+  f32x16_t acc[2][4];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  const int nst = (n + RK - 1) / RK;
+  issue(0);
+  if (nst > 1) issue(1);
+  for (int st = 0; st < nst; ++st) {
+    // this stage's loads have landed (only the next stage's six may fly), in
+    // every wave once all have passed the barrier; that barrier also ends
+    // every wave's reads of the slot the stage after next overwrites
+    if (st + 1 < nst) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);                // vmcnt(0)
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (st + 2 < nst) issue(st + 2);
+    const unsigned char *sa = &ring[st % RS][0];
+    const unsigned char *sbh = sa + R_A, *sbl = sa + R_A + R_B;
+#pragma unroll
+    for (int kk = 0; kk < RK; kk += 16) {
+      const int kq = kk + 8 * (lane >> 5);   // first of my 8 j
+      bf16x8_t fah[2], fbh[4], fbl[4];
+      for (int m = 0; m < 2; ++m) {
+        const int row = wi * 64 + m * 32 + (lane & 31);
+        const int slot = (kq >> 3) ^ ((row >> 2) & 3);
+        const uint4 rh = *reinterpret_cast<const uint4 *>(sa + (row * 4 + slot) * 16);
+        __builtin_memcpy(&fah[m], &rh, 16);
+      }
+      for (int q = 0; q < 4; ++q) {
+        const int col = wj * 128 + q * 32 + (lane & 31);
+        const int o = ((kq >> 3) * RN + col) * 16;
+        const uint4 uh = *reinterpret_cast<const uint4 *>(sbh + o);
+        const uint4 ul = *reinterpret_cast<const uint4 *>(sbl + o);
+        __builtin_memcpy(&fbh[q], &uh, 16);
+        __builtin_memcpy(&fbl[q], &ul, 16);
+      }
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbl[q], acc[m][q], 0, 0, 0);
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbh[q], acc[m][q], 0, 0, 0);
+    }
+  }
+
+  const float inv_n = 1.0f / float(n);
+  const float inv_h2 = float(1.0 / h2[0]);
+  bool bad = false;
+  if constexpr (RULE) {
+    // a step rule with per-coordinate state: one element at a time
+    for (int m = 0; m < 2; ++m)
+      for (int r = 0; r < 16; ++r) {
+        const int i = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i >= n) continue;
+        const float si = s[i] * inv_h2;
+        for (int q = 0; q < 4; ++q) {
+          const long long a = a0 + wj * 128 + q * 32 + (lane & 31);
+          if (a >= d) continue;
+          const long long e = (long long)i * d + a;
+          const float xe = x[e];
+          const float p = fmaf(si, xe - xbar[a], acc[m][q][r]) * inv_n;
+          phi[e] = p;
+          float v = xe + opt_step(opt, e, p, eps);
+          if (lo) v = fminf(fmaxf(v, lo[a]), hi[a]);
+          bad |= !isfinite(v);
+          x[e] = v;
+        }
+      }
+  } else {
+    // Plain steps in four batches of eight result registers (32 elements):
+    // every x of a batch is loaded before any store (the stores to phi and x
+    // could alias them as far as the compiler knows, which would otherwise
+    // serialise each load behind the previous element's stores), and the next
+    // batch's loads go out before this batch's stores, since loads and stores
+    // retire through one in-order counter: waiting for loads issued after the
+    // stores would wait for the stores too.  Batch b covers sub-tile b / 2,
+    // registers 8 (b % 2) .. + 7; element (r, q) of sub-tile m sits at
+    // el + (m 32 + 8 (r / 4) + r % 4) d + 32 q.
+    const int lrow = wi * 64 + 4 * (lane >> 5);      // my first local row
+    const int lcol = wj * 128 + (lane & 31);         // my first local column
+    const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
+    float xb[4], lov[4], hiv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long a = a0 + lcol + q * 32;
+      xb[q] = a < d ? xbar[a] : 0.0f;
+      lov[q] = (lo && a < d) ? lo[a] : 0.0f;
+      hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
+    }
+    // local row (relative to my first) of register r of sub-tile m
+    auto lrow_of = [](int m, int r) { return m * 32 + 8 * (r >> 2) + (r & 3); };
+    float xv[2][8][4], si[2][8];
+    // Loads are unconditional (elements outside the ensemble read x[0] and
+    // s[0] and are never used), so no branch separates them from each other.
+    auto load_batch = [&](int b, float (&xvb)[8][4], float (&sib)[8]) {
+      const int m = b >> 1, rb = (b & 1) * 8;
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int lr = lrow_of(m, rb + rr);
+        const int i = i0 + lrow + lr;
+        sib[rr] = s[i < n ? i : 0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool in = i < n && a0 + lcol + q * 32 < d;
+          xvb[rr][q] = x[in ? el + (long long)lr * d + q * 32 : 0];
+        }
+      }
+    };
+    load_batch(0, xv[0], si[0]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b + 1 < 4) load_batch(b + 1, xv[(b + 1) & 1], si[(b + 1) & 1]);
+      const int m = b >> 1, rb = (b & 1) * 8;
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int lr = lrow_of(m, rb + rr);
+        if (i0 + lrow + lr >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (a0 + lcol + q * 32 >= d) continue;
+          const long long e = el + (long long)lr * d + q * 32;
+          const float xe = xv[b & 1][rr][q];
+          const float p = fmaf(si[b & 1][rr] * inv_h2, xe - xb[q], acc[m][q][rb + rr]) * inv_n;
+          phi[e] = p;
+          float v = xe + eps * p;
+          if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
+          bad |= !isfinite(v);
+          x[e] = v;
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+}
+
 // ---- host ---------------------------------------------------------------------
 
 // Host-side validation of one step (everything that can fail before a launch).
@@ -1554,12 +1779,25 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     bpair_kernel<<<dim3(unsigned((P.dp + 255) / 256), unsigned(ngroups)), dim3(256), 0, s>>>(
         g, x, P.xbar, vq, P.h2, P.bph, P.bpl, n, d, P.dp);
     VIP_LAUNCH_CHECK();
-    const int vblocks = (n + VM - 1) / VM;
-    const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
-    auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x2_kernel<false> : update_bf16x2_kernel<true>;
-    kern<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
-        P.khi, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, ulo, uhi, n, d,
-        vblocks, float(eps), oa, P.status);
+    // the ring kernel addresses K and the B pairs with 32-bit byte offsets
+    const bool ring = kUpdateRing && (long long)n * P.ldk * 2 < (1LL << 31) &&
+                      (long long)(P.ldk / 2) * P.dp * 4 < (1LL << 31);
+    if (ring) {
+      const int rblocks = (n + RM - 1) / RM;
+      const long long rtiles = (long long)rblocks * ((d + RN - 1) / RN);
+      auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x2_ring_kernel<false>
+                                          : update_bf16x2_ring_kernel<true>;
+      kern<<<dim3(unsigned((rtiles + 7) / 8 * 8)), dim3(RT), 0, s>>>(
+          P.khi, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, ulo, uhi, n, d,
+          rblocks, float(eps), oa, P.status);
+    } else {
+      const int vblocks = (n + VM - 1) / VM;
+      const long long vtiles = (long long)vblocks * ((d + VN - 1) / VN);
+      auto *kern = oa.kind == VIP_OPT_SGD ? update_bf16x2_kernel<false> : update_bf16x2_kernel<true>;
+      kern<<<dim3(unsigned((vtiles + 7) / 8 * 8)), dim3(VT), 0, s>>>(
+          P.khi, P.ldk, P.bph, P.bpl, P.dp, P.xbar, P.s, P.h2, x, P.phi, ulo, uhi, n, d,
+          vblocks, float(eps), oa, P.status);
+    }
   } else {
     auto *kern = oa.kind == VIP_OPT_SGD ? update_mfma_kernel<false> : update_mfma_kernel<true>;
     kern<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
