@@ -298,6 +298,130 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
       }
 }
 
+// The BF16 Gram in 256 x 256 blocks of the upper triangle, one block per
+// compute unit, 8 waves (4 x 2) of 64 x 128 (2 x 4 tiles of 32 x 32).  The
+// operands stream through a ring of four LDS stages of 32 coordinates (A and
+// B rows: 16 KB each; a diagonal block loads A only and reads it for both) by
+// 16-byte loads that write LDS directly, three stages ahead of the matrix
+// instructions, with one barrier per stage.  Chunk c (8 coordinates) of row r
+// sits in slot c ^ ((r >> 2) & 3) of the row's four, so that the fragment
+// reads of 16 consecutive rows meet distinct banks.  Rows past n and
+// coordinates past the split's end read as zeros (offsets beyond the range).
+// The loads are inline assembly with explicit counter waits, for the reason
+// given at update_bf16x2_ring_kernel.  Needs rows of a multiple of 8
+// coordinates (16-byte aligned) and n d 2 bytes below 2^31.
+constexpr int G2B = 256, G2K = 32, G2S = 4, G2T = 512;
+constexpr bool kGramRing = true;
+constexpr int G2_OP = G2B * G2K * 2, G2_STAGE = 2 * G2_OP;
+__global__ __launch_bounds__(G2T) __attribute__((amdgpu_waves_per_eu(2, 2))) void gram_bf16_ring_kernel(
+    const uint16_t *xc16, float *part, int n, long long d, long long kspan, int nbt) {
+  __shared__ __attribute__((aligned(16))) unsigned char ring[G2S][G2_STAGE];
+  const int nup = nbt * (nbt + 1) / 2;
+  const int per = int(gridDim.x) >> 3;
+  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  if (tb >= nup * int((d + kspan - 1) / kspan)) return;
+  const int split = tb / nup;
+  int bi, bj;
+  upper_block(tb - split * nup, nbt, bi, bj);
+  const int i0 = bi * G2B, j0 = bj * G2B;
+  const bool diag = bi == bj;
+  const long long k0 = (long long)split * kspan;
+  const long long k1 = min(d, k0 + kspan);
+  const int nst = int((k1 - k0 + G2K - 1) / G2K);
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wi = w >> 1, wj = w & 1;
+
+  typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+  U32x4 rx;
+  {
+    const uint64_t b = reinterpret_cast<uint64_t>(xc16);
+    rx.x = __builtin_amdgcn_readfirstlane(uint32_t(b));
+    rx.y = __builtin_amdgcn_readfirstlane(uint32_t(b >> 32)) & 0xffffu;
+    rx.z = __builtin_amdgcn_readfirstlane(uint32_t(n) * uint32_t(d) * 2u);
+    rx.w = 0x00020000u;
+  }
+  const uint32_t ring0 = uint32_t(reinterpret_cast<uintptr_t>(
+      (__attribute__((address_space(3))) unsigned char *)&ring[0][0]));
+  // My loads of a stage: A loads w and w + 8 of the 16 (rows 16 q + lane / 4),
+  // then (off the diagonal) B loads w and w + 8.
+  auto issue = [&](int st) {
+    const long long kb = k0 + (long long)st * G2K;
+    const uint32_t base = ring0 + uint32_t((st % G2S) * G2_STAGE);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k >= 2 && diag) break;
+      const int q = w + 8 * (k & 1);
+      const int row = 16 * q + (lane >> 2);
+      const int chunk = (lane & 3) ^ ((row >> 2) & 3);
+      const int grow = (k < 2 ? i0 : j0) + row;
+      const long long kc = kb + chunk * 8;
+      const uint32_t m0 = base + uint32_t((k >= 2 ? G2_OP : 0) + q * 16 * 64);
+      const uint32_t off = (grow < n && kc < k1) ? uint32_t(((long long)grow * d + kc) * 2)
+                                                 : 0x80000000u;
+      uint32_t keep;
+      asm volatile(
+          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+          "buffer_load_dwordx4 %2, %3, 0 offen lds\n\ts_mov_b32 m0, %0"
+          : "=&s"(keep)
+          : "s"(m0), "v"(off), "s"(rx)
+          : "memory");
+    }
+  };
+
+  f32x16_t acc[2][4];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  for (int st = 0; st < 3 && st < nst; ++st) issue(st);
+  for (int st = 0; st < nst; ++st) {
+    // this stage has landed once only the later stages' loads may fly (two
+    // loads a stage on the diagonal, four off it)
+    const int newer = min(nst - 1 - st, 2);
+    if (diag) {
+      if (newer == 2) __builtin_amdgcn_s_waitcnt(0x0F74);        // vmcnt(4)
+      else if (newer == 1) __builtin_amdgcn_s_waitcnt(0x0F72);   // vmcnt(2)
+      else __builtin_amdgcn_s_waitcnt(0x0F70);
+    } else {
+      if (newer == 2) __builtin_amdgcn_s_waitcnt(0x0F78);        // vmcnt(8)
+      else if (newer == 1) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
+      else __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (st + 3 < nst) issue(st + 3);
+    const unsigned char *sa = &ring[st % G2S][0];
+    const unsigned char *sb = diag ? sa : sa + G2_OP;
+#pragma unroll
+    for (int kk = 0; kk < G2K; kk += 16) {
+      const int c = (kk + 8 * (lane >> 5)) >> 3;   // my chunk of 8 coordinates
+      bf16x8_t fa[2], fb[4];
+      for (int m = 0; m < 2; ++m) {
+        const int row = wi * 64 + m * 32 + (lane & 31);
+        const uint4 v = *reinterpret_cast<const uint4 *>(sa + (row * 4 + (c ^ ((row >> 2) & 3))) * 16);
+        __builtin_memcpy(&fa[m], &v, 16);
+      }
+      for (int q = 0; q < 4; ++q) {
+        const int row = wj * 128 + q * 32 + (lane & 31);
+        const uint4 v = *reinterpret_cast<const uint4 *>(sb + (row * 4 + (c ^ ((row >> 2) & 3))) * 16);
+        __builtin_memcpy(&fb[q], &v, 16);
+      }
+      for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 4; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fb[q], acc[m][q], 0, 0, 0);
+    }
+  }
+  float *P = part + (long long)split * n * n;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = j0 + wj * 128 + q * 32 + (lane & 31);
+        if (row < n && col < n) P[(long long)row * n + col] = acc[m][q][r];
+      }
+}
+
 // ---- Gram, FP32 matrix cores -------------------------------------------------
 // Same 128x128 blocks and k splits; 4 waves, each a 64x64 sub-block as 2x2
 // tiles of v_mfma_f32_32x32x2_f32 (lane l holds A[l % 32][l / 32] and
@@ -1725,12 +1849,21 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   VIP_LAUNCH_CHECK();
   const int nup = P.nbt * (P.nbt + 1) / 2;
   const bool g16 = gram_prec == VIP_GRAM_BF16;
-  const int gsplits = g16 ? P.splits16 : P.splits;
-  dim3 ggrid(unsigned((nup * gsplits + 7) / 8 * 8));
-  if (g16)
-    gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan16, P.nbt);
-  else
-    gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, sq, P.part, n, d, P.kspan, P.nbt);
+  // the ring Gram reads 16-byte chunks of rows (a multiple of 8 coordinates)
+  // at 32-bit byte offsets
+  const bool gring = g16 && kGramRing && d % 8 == 0 && (long long)n * d * 2 < (1LL << 31);
+  const int gsplits = gring ? P.splits2 : g16 ? P.splits16 : P.splits;
+  if (gring) {
+    const int nup2 = P.nbt2 * (P.nbt2 + 1) / 2;
+    gram_bf16_ring_kernel<<<dim3(unsigned((nup2 * gsplits + 7) / 8 * 8)), dim3(G2T), 0, s>>>(
+        P.xc16, P.part, n, d, P.kspan2, P.nbt2);
+  } else {
+    dim3 ggrid(unsigned((nup * gsplits + 7) / 8 * 8));
+    if (g16)
+      gram_bf16_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc16, P.part, n, d, P.kspan16, P.nbt);
+    else
+      gram_f32_kernel<<<ggrid, dim3(256), 0, s>>>(P.xc, sq, P.part, n, d, P.kspan, P.nbt);
+  }
   VIP_LAUNCH_CHECK();
   {
     const int ntile = (n + DT - 1) / DT;

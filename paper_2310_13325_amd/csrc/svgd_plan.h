@@ -26,6 +26,8 @@ struct SvgdPlan {
   int nbt = 0;
   int splits = 0, splits16 = 0;        // k splits of the FP32 and of the BF16 Gram
   long long kspan = 0, kspan16 = 0;    // coordinates per split, same order
+  int nbt2 = 0, splits2 = 0;           // BF16 Gram in 256 x 256 blocks (LDS ring): blocks a side, k splits
+  long long kspan2 = 0;
   size_t bytes = 0;
 };
 
@@ -60,6 +62,22 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->splits = int((d + P->kspan - 1) / P->kspan);
   P->kspan16 = span_of(sb16);
   P->splits16 = int((d + P->kspan16 - 1) / P->kspan16);
+  // 256 x 256 blocks, one per compute unit: as many splits as keep the blocks
+  // within one round of the 256 units and spread them most evenly
+  P->nbt2 = (n + 255) / 256;
+  {
+    const int nup2 = P->nbt2 * (P->nbt2 + 1) / 2;
+    int sb2 = 1;
+    double best = 0.0;
+    for (int s = 1; s <= 64; ++s) {
+      const long long b = (long long)nup2 * s;
+      if (b > 256 && s > 1) break;
+      const double even = double(b) / 256.0;
+      if (even > best) best = even, sb2 = s;
+    }
+    P->kspan2 = span_of(sb2);
+    P->splits2 = int((d + P->kspan2 - 1) / P->kspan2);
+  }
   const size_t nn = size_t(n) * size_t(n), nd = size_t(n) * size_t(d);
   Arena A;
   A.base = base;
@@ -69,7 +87,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->vq = A.take<float>(size_t(d));
   P->xc = A.take<float>(nd);
   P->xc16 = A.take<uint16_t>(nd);
-  P->part = A.take<float>(size_t(std::max(P->splits, P->splits16)) * nn);
+  P->part = A.take<float>(size_t(std::max(std::max(P->splits, P->splits16), P->splits2)) * nn);
   P->D = A.take<float>(nn);
   P->K = A.take<float>(nn);
   P->s = A.take<float>(size_t(n));
