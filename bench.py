@@ -742,12 +742,15 @@ def main():
         # Matrix-core work of one BF16-path step against the dense BF16 peak,
         # two ways: algorithmic -- the upper Gram (the 136 upper 128 x 128
         # blocks of 256, 2 n^2 d x 136/256) and one product K B (2 n^2 d); and
-        # executed -- the update runs that product as two BF16 products (K
-        # times the two halves of the split B)
+        # executed -- the Gram kernel computes whole upper 256 x 256 blocks
+        # (36 of 64 at n = 2048) and the update runs the product as two BF16
+        # products (K times the two halves of the split B)
         nn_d = 2.0 * case.n * case.n * case.d
         nb = (case.n + 127) // 128
         gram = nn_d * (nb * (nb + 1) / 2) / nb ** 2
-        alg, executed = gram + nn_d, gram + 2.0 * nn_d
+        nb2 = (case.n + 255) // 256
+        gram_run = nn_d * (nb2 * (nb2 + 1) / 2) / nb2 ** 2
+        alg, executed = gram + nn_d, gram_run + 2.0 * nn_d
         rate = svgd["bf16_gram"]
         svgd["bf16_path_matrix_core"] = {
             "algorithmic_flops_per_step": alg, "algorithmic_TFLOPs": round(alg * rate / 1e12, 1),
