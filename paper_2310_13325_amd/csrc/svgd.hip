@@ -1836,8 +1836,9 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
 
   const bool diag = kernel == VIP_KERNEL_DIAG_VAR;
   float *sq = diag ? P.sq : nullptr, *vq = diag ? P.vq : nullptr;
-  // the BF16 path without noise never reads the FP32 Xc (it recomputes x - xbar)
-  const bool split_update = !noise && gram_prec == VIP_GRAM_BF16;
+  // the BF16 path never reads the FP32 Xc (it recomputes x - xbar); with
+  // noise the update leaves the clip to the noise pass, as on the FP32 path
+  const bool split_update = gram_prec == VIP_GRAM_BF16;
   // the register cache addresses X with 32-bit byte offsets, up to row 32 CACHE
   const unsigned long long rows = (unsigned long long)std::max(n, CENTRE_GROUPS * CENTRE_CACHE);
   auto *centre = rows * (unsigned long long)d * 4ull < (1ull << 31)
