@@ -111,8 +111,9 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   __shared__ int rmapl[kPipeRmap];    // receiver id at (receiver row k, column X), -1: none
 
   // This block's run of tiles: XCD x = blockIdx % 8 owns [x per, (x + 1) per),
-  // its j-th block the j-th of J runs of that range.  Tile index t stands for
-  // tile position t / npairs of local pair t % npairs.
+  // its j-th block the tiles j, j + J, j + 2 J, ... of that range.  Local tile
+  // lt of a problem stands for position lt % tiles_per_pair of its local pair
+  // lt / tiles_per_pair.
   const int J = int(gridDim.x) >> 3;
   const int total = total_of(kp0);
   const int per = (total + 7) >> 3;
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(EX *(EZ / RZ)) void fd_pipe(PipeParams<MULTI> args)
   int zl0 = (int(threadIdx.x) / EX) * RZ;  // first extended-tile row of my strip
 
   // once per block: zero the padding cells of both u buffers (every other cell
-  // is written before it is read); wavelet samples of this launch's steps
+  // is written before it is read)
   {
     constexpr int PR = 4 * LW, PC = 4 * EZ;   // padding rows, padding columns
     for (int e = threadIdx.x; e < 2 * (PR + PC); e += NTHREADS) {
