@@ -353,9 +353,10 @@ vip_status vip_svgd_layout_of(int32_t n, int64_t d, vip_svgd_layout *out);
  * Distances come from the Gram matrix of the centred particles, on BF16 matrix
  * cores or in FP32 (gram_prec).  The product K (G - X_c / h^2) behind phi runs
  * in FP32 on the FP32 matrix cores with VIP_GRAM_FP32; with VIP_GRAM_BF16 it
- * runs on the BF16 matrix cores with each FP32 operand split into a BF16 pair
- * (hi + lo, products hi hi + hi lo + lo hi, FP32 accumulation: within 2^-16 of
- * each product, below the error of the BF16 Gram).  h2_out: device double [1]
+ * runs on the BF16 matrix cores with K rounded to BF16 and the FP32 operand B
+ * = G - X_c / h^2 split into a BF16 pair (B = hi + lo, products K hi + K lo,
+ * FP32 accumulation): phi within about 4e-5 relative L2 at n = 2048, a part
+ * of the error the BF16 Gram already puts into K.  h2_out: device double [1]
  * or NULL. */
 vip_status vip_svgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
                          int32_t bw_mode, double h_fixed, int32_t gram_prec,
@@ -424,7 +425,7 @@ vip_status vip_svgd_step_ex(vip_ctx *ctx, int32_t n, int64_t d, float *x, const 
  * K/n (eq:matrixDK, eq:noise_term; factorised in FP64 on the device, with
  * jitter 1e-12 trace/n x10 per retry, at most 6 retries), then the prior clip.
  * n <= 128 factorises in one workgroup with the matrix in LDS; larger n by
- * right-looking 64-column panels over the whole GPU, any n.  A factorisation
+ * right-looking 32-column panels over the whole GPU, any n.  A factorisation
  * that needs jitter (numerically coincident particles) reruns in one
  * workgroup with the matrix in global memory: correct, but slow for large n
  * (VIP_FLAG_JITTER reports it).  The direction phi is formed as in

@@ -332,7 +332,7 @@ def test_diag_matrix_kernel_ssvgd_matches_oracle():
 @pytest.mark.parametrize("n", [129, 600, 1000, 2048])
 def test_ssvgd_blocked_cholesky_matches_oracle(n):
     """sSVGD beyond one workgroup's LDS (n > 128): the blocked FP64 Cholesky of
-    K/n (64-column panels) and the noise L Xi with the same normals on both
+    K/n (32-column panels) and the noise L Xi with the same normals on both
     sides, d = 4096, FP32 Gram: L <= 1e-5, x' <= 1e-6, displacement <= 1e-3.
     The displacement (about 0.5 per coordinate here) is bounded by the FP32
     storage of x' itself: half an ulp at x ~ 3000 is 1.2e-4, so its relative
