@@ -387,3 +387,32 @@ def test_ssvgd_blocked_cholesky_coincident_particles(n, ndup):
     assert np.abs(L @ L.T - A).max() <= 1e-6 * A.max()
     assert e <= 1e-5
     c._ws.pop("chol_dup", None)
+
+
+@pytest.mark.parametrize("n", [600, 2048])
+def test_ssvgd_bf16_path_matches_oracle(n):
+    """sSVGD on the BF16 path (BF16 Gram in 256 x 256 blocks, K in BF16 times
+    the split B on the BF16 matrix cores, blocked FP64 Cholesky, noise L Xi on
+    the FP32 matrix cores) with the same normals on both sides, d = 4096: phi
+    and L to 1e-3 relative L2 (the BF16 path's tolerance), the displacement
+    x' - x to 1e-3."""
+    from oracle import cref
+    from tests.cases import workers
+    d, eps = 4096, 20.0
+    X, G = _ensemble(n, d, 80 + n)
+    xi = np.random.default_rng(81 + n).standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), eps, xi=dev(xi), gram_prec=vb.VIP_GRAM_BF16,
+                           ws_tag=f"ssvgd16_{n}")
+    flags = c.poll(ws)
+    D, K, h2, phi, L = _inspect(ws, n, d)
+    info = osvgd.svgd_direction(X, G, D=cref.sqdist(X, workers=workers()))
+    eta, L_ref, retries = osvgd.ssvgd_noise(info["K"], eps, xi)
+    Xr = X + eps * info["phi"] + eta
+    xn = x.cpu().numpy().astype(np.float64)
+    ephi, eL, edX = rel(phi, info["phi"]), rel(L, L_ref), rel(xn - X, Xr - X)
+    print(f"sSVGD BF16 path n={n}: phi {ephi:.2e}, L {eL:.2e}, displacement {edX:.2e}", flush=True)
+    assert flags & ~vb.VIP_FLAG_JITTER == 0 and retries == 0
+    assert ephi <= 1e-3 and eL <= 1e-3 and edX <= 1e-3
+    c._ws.pop(f"ssvgd16_{n}", None)
