@@ -280,14 +280,11 @@ def _timed(torch, fn, reps):
     return (time.perf_counter() - t) / reps
 
 
-def c1_rate(ctx, vb, synth, torch, configs, graph_after=False):
+def c1_rate(ctx, vb, synth, torch, configs):
     """c1: the plain SVGD-FWI loop, 8 particles x 4 shots on 64 x 64 cells,
     nt = 500: 20 iterations of the gradients plus an SVGD step (FP32 Gram,
-    median bandwidth, clip).  The gradient calls replay through the library's
-    hipGraph mode: at this size a gradient is about 400 short launches.  The
-    context's graph mode is set to `graph_after` on return."""
+    median bandwidth, clip)."""
     prob = configs.C1
-    ctx.set_graph_mode(True)
     S1 = setup(prob, ctx, vb, synth, torch, prob.np)
     n, d = prob.np, prob.d
     # the tile shape the library picks for this small grid (32 pairs), not the
@@ -315,12 +312,10 @@ def c1_rate(ctx, vb, synth, torch, configs, graph_after=False):
     steps = configs.SVGD_STEPS_C1
     tile = ctx.tile_for(S1["grid"], n * prob.ns)
     ctx.set_tile(main_tile)
-    ctx.set_graph_mode(graph_after)
     return {"workload": "c1: 64x64 at 10 m, nt=500, 4 shots, 64 receivers, 8 particles, "
                         f"{steps} SVGD iterations (gradients + FP32-Gram SVGD step)",
             "svgd_iterations_per_s": round(steps / sec, 1),
-            "particle_gradients_per_s": round(steps * n / sec, 1), "tile": tile,
-            "graph": True}
+            "particle_gradients_per_s": round(steps * n / sec, 1), "tile": tile}
 
 
 def c3_rate(ctx, vb, synth, torch, configs, autotune, fixed=None):
@@ -668,7 +663,7 @@ def main():
         work = {}
         which = [w.strip() for w in args.workloads.split(",") if w.strip()]
         if "c1" in which:
-            work["c1"] = c1_rate(ctx, vb, synth, torch, configs, graph_after=args.graph)
+            work["c1"] = c1_rate(ctx, vb, synth, torch, configs)
             log(f"c1: {work['c1']}")
         if "c4" in which:
             work["c4"] = c4_rates(ctx, vb, synth, torch, configs, autotune)
