@@ -809,7 +809,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 
 __global__ __launch_bounds__(256) void chol_panel_kernel(double *A, int n, int k0,
                                                          uint32_t *state) {
-  if (state[0]) return;
   __shared__ double Ls[CB][CB + 1];   // L11
   __shared__ double Li[CB][CB + 1];   // L11^-1 (lower)
   __shared__ double As[CR][CB + 1];   // this block's rows of A21
@@ -817,22 +816,37 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double *A, int n, int k
   const int t = threadIdx.x;
   const int b = min(CB, n - k0);
   const int r0 = k0 + CB + (int(blockIdx.x) - 1) * CR;   // first A21 row (blocks >= 1)
-  if (blockIdx.x > 0)   // stage A21 while wave 0 factors
-    for (int e = t; e < CR * CB; e += 256) {
-      const int r = e / CB, k = e - (e / CB) * CB;
-      As[r][k] = r0 + r < n ? A[(long long)(r0 + r) * n + k0 + k] : 0.0;
-    }
+  // the failure flag is read together with the block's first loads (all of
+  // them read A only), so that the two latencies overlap
+  const uint32_t failed = state[0];
+  // lane i < CB of wave 0 holds row i of the diagonal block (identity beyond
+  // the matrix); lanes CB.. repeat row CB - 1 and are never read
+  const int i = t < CB ? t : CB - 1;
+  double r[CB];
   if (t < 64) {
-    // lane i < CB holds row i of the diagonal block (identity beyond the
-    // matrix); lanes CB.. repeat row CB - 1 and are never read
-    const int i = t < CB ? t : CB - 1;
-    double r[CB];
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
       double v = i == j ? 1.0 : 0.0;
       if (i < b && j < b && j <= i) v = A[(long long)(k0 + i) * n + k0 + j];
       r[j] = v;
     }
+  }
+  if (blockIdx.x > 0) {   // stage A21 while wave 0 factors (unrolled: all loads in flight at once)
+    constexpr int SE = CR * CB / 256;
+    double v[SE];
+#pragma unroll
+    for (int q = 0; q < SE; ++q) {
+      const int e = t + 256 * q, r = e / CB, k = e - (e / CB) * CB;
+      v[q] = r0 + r < n ? A[(long long)(r0 + r) * n + k0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < SE; ++q) {
+      const int e = t + 256 * q, r = e / CB, k = e - (e / CB) * CB;
+      As[r][k] = v[q];
+    }
+  }
+  if (failed) return;   // uniform over the block
+  if (t < 64) {
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < CB; ++k) {
@@ -896,7 +910,6 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double *A, int n, int k
 // (ti, tj) with tj <= ti), 256 threads with 4 x 4 outputs each.
 __global__ __launch_bounds__(256) void chol_update_kernel(double *A, int n, int k0,
                                                           uint32_t *state) {
-  if (state[0]) return;
   __shared__ double Li[64][CB + 1], Lj[64][CB + 1];
   const int r0 = k0 + CB;
   const int b = CB;   // update panels are always full: a short last panel has no trailing part
@@ -908,13 +921,37 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double *A, int n, int 
   const int tj = tb - ti * (ti + 1) / 2;
   const int i0 = r0 + 64 * ti, j0 = r0 + 64 * tj;
   const int t = threadIdx.x;
-  for (int e = t; e < 64 * CB; e += 256) {
-    const int r = e / CB, k = e - (e / CB) * CB;
-    Li[r][k] = i0 + r < n ? A[(long long)(i0 + r) * n + k0 + k] : 0.0;
-    Lj[r][k] = j0 + r < n ? A[(long long)(j0 + r) * n + k0 + k] : 0.0;
+  const int ty = t >> 4, tx = t & 15;
+  // the failure flag, the panel columns and this thread's old trailing
+  // entries are all read up front (the staging loop unrolled), so that their
+  // latencies overlap
+  const uint32_t failed = state[0];
+  constexpr int SE = 64 * CB / 256;   // staged elements per thread and operand
+  double vi[SE], vj[SE];
+#pragma unroll
+  for (int q = 0; q < SE; ++q) {
+    const int e = t + 256 * q, r = e / CB, k = e - (e / CB) * CB;
+    vi[q] = i0 + r < n ? A[(long long)(i0 + r) * n + k0 + k] : 0.0;
+    vj[q] = j0 + r < n ? A[(long long)(j0 + r) * n + k0 + k] : 0.0;
+  }
+  double old[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + ty + 16 * r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + tx + 16 * c;
+      old[r][c] = (i < n && j <= i) ? A[(long long)i * n + j] : 0.0;
+    }
+  }
+  if (failed) return;   // uniform over the block
+#pragma unroll
+  for (int q = 0; q < SE; ++q) {
+    const int e = t + 256 * q, r = e / CB, k = e - (e / CB) * CB;
+    Li[r][k] = vi[q];
+    Lj[r][k] = vj[q];
   }
   __syncthreads();
-  const int ty = t >> 4, tx = t & 15;
   double acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -940,7 +977,7 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double *A, int n, int 
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int j = j0 + tx + 16 * c;
-      if (j <= i && j < n) A[(long long)i * n + j] -= acc[r][c];
+      if (j <= i && j < n) A[(long long)i * n + j] = old[r][c] - acc[r][c];
     }
   }
 }
@@ -1204,7 +1241,11 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
 // layouts as update_mfma_kernel, with A = L and B = Xi: the A tile
 // As[k][i] = L[i0 + i][j0 + k] is a row segment of the transposed FP32 copy
 // LfT, and since L is lower triangular a block of rows i0 .. i0 + UM - 1 takes
-// j < i0 + UM only (about half the product overall).
+// j < i0 + UM only (about half the product overall).  A block's work grows
+// with its row block, so the blocks go out longest first: XCD x = blockIdx % 8
+// owns the column blocks [x nc / 8, (x + 1) nc / 8), and its k-th block takes
+// row block mblocks - 1 - k / ncx, column block k % ncx of that range (the
+// grid is 8 mblocks ceil(nc / 8) blocks).
 __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const float *xi,
                                                         const float *vq, float *x,
                                                         const float *lo, const float *hi, int n,
@@ -1212,12 +1253,13 @@ __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const 
                                                         float scale, uint32_t *status) {
   __shared__ __attribute__((aligned(16))) float As[UK][UM + UP];   // As[k][i] = L[i0 + i][j0 + k]
   __shared__ __attribute__((aligned(16))) float Bs[UK][UN + UP];   // Bs[k][a] = Xi[j0 + k][a0 + a]
-  const int per = int(gridDim.x) >> 3;
-  const int tb = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
-  const int nt = mblocks * int((d + UN - 1) / UN);
-  if (tb >= nt) return;
-  const int i0 = (tb % mblocks) * UM;
-  const long long a0 = (long long)(tb / mblocks) * UN;
+  const long long nc = (d + UN - 1) / UN;
+  const int xcd = int(blockIdx.x) & 7, kb = int(blockIdx.x) >> 3;
+  const long long cb0 = xcd * nc / 8;
+  const int ncx = int((xcd + 1) * nc / 8 - cb0);
+  if (kb >= mblocks * ncx) return;
+  const int i0 = (mblocks - 1 - kb / ncx) * UM;
+  const long long a0 = (cb0 + kb % ncx) * UN;
   const int jend = min(n, i0 + UM);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
@@ -1976,7 +2018,8 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     const int nvec = (d % 4 == 0) && (n % 4 == 0) &&
                      (reinterpret_cast<uintptr_t>(xin) % 16 == 0) &&
                      (reinterpret_cast<uintptr_t>(P.Lf) % 16 == 0);
-    noise_mfma_kernel<<<dim3(unsigned((ntiles + 7) / 8 * 8)), dim3(UT), 0, s>>>(
+    const long long nxcd = (((d + UN - 1) / UN) + 7) / 8;   // column blocks per XCD, at most
+    noise_mfma_kernel<<<dim3(unsigned(8 * mblocks * nxcd)), dim3(UT), 0, s>>>(
         P.Lf, xin, vq, x, lo, hi, n, d, mblocks, nvec, float(std::sqrt(2.0 * eps)), P.status);
   }
   VIP_LAUNCH_CHECK();
