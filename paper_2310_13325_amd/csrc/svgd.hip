@@ -852,8 +852,15 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double *A, int n, int k
     for (int k = 0; k < CB; ++k) {
       const double p = readlane_f64(r[k], k);   // the pivot, uniform
       ok = ok && p > 0.0;
-      const double piv = p > 0.0 ? sqrt(p) : 1.0;
-      const double l = r[k] / piv;
+      // sqrt(p) and the column's division by it both through 1/sqrt(p), the
+      // hardware estimate refined by two Newton steps, so that the step's
+      // dependency chain holds no square root or division
+      const double pp = p > 0.0 ? p : 1.0;
+      double rs = __builtin_amdgcn_rsq(pp);
+#pragma unroll
+      for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-pp * rs, rs, 1.0), rs);
+      const double piv = pp * rs;
+      const double l = r[k] * rs;
       r[k] = i == k ? piv : (i > k ? l : r[k]);
 #pragma unroll
       for (int j = k + 1; j < CB; ++j) r[j] = fma(-r[k], readlane_f64(r[k], j), r[j]);
@@ -876,14 +883,16 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double *A, int n, int k
   }
   if (blockIdx.x == 0) return;
   if (t < CB) {
-    // column j = t of L11^-1: L11 x = e_j by forward substitution
+    // column j = t of L11^-1: L11 x = e_j by forward substitution, each
+    // diagonal reciprocal formed outside the chain from x[0] to x[CB - 1]
     double x[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
+      const double rdq = 1.0 / Ls[q][q];
       double v = q == t ? 1.0 : 0.0;
 #pragma unroll
       for (int m = 0; m < q; ++m) v = fma(-Ls[q][m], x[m], v);
-      x[q] = v / Ls[q][q];
+      x[q] = v * rdq;
     }
 #pragma unroll
     for (int q = 0; q < CB; ++q) Li[q][t] = x[q];

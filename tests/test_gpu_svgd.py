@@ -333,7 +333,9 @@ def test_diag_matrix_kernel_ssvgd_matches_oracle():
 def test_ssvgd_blocked_cholesky_matches_oracle(n):
     """sSVGD beyond one workgroup's LDS (n > 128): the blocked FP64 Cholesky of
     K/n (32-column panels) and the noise L Xi with the same normals on both
-    sides, d = 4096, FP32 Gram: L <= 1e-5, x' <= 1e-6, displacement <= 1e-3.
+    sides, d = 4096, FP32 Gram: L <= 1e-5, x' <= 1e-6, displacement <= 1e-3,
+    and L L^T within 1e-13 (relative to its largest entry) of K/n formed in
+    FP64 from the library's own D and h^2.
     The displacement (about 0.5 per coordinate here) is bounded by the FP32
     storage of x' itself: half an ulp at x ~ 3000 is 1.2e-4, so its relative
     error cannot go much below 1e-4 whatever the arithmetic."""
@@ -354,10 +356,15 @@ def test_ssvgd_blocked_cholesky_matches_oracle(n):
     Xr = X + eps * info["phi"] + eta
     xn = x.cpu().numpy().astype(np.float64)
     eL, eX, edX = rel(L, L_ref), rel(xn, Xr), rel(xn - X, Xr - X)
-    print(f"  L {eL:.2e}, x' {eX:.2e}, displacement {edX:.2e}, oracle retries {retries}",
-          flush=True)
+    # backward error of the factorisation itself, against K/n formed in FP64
+    # from the library's own D and h^2
+    A = np.exp(-D.astype(np.float64) / (2.0 * h2)) / n
+    eB = np.abs(L @ L.T - A).max() / A.max()
+    print(f"  L {eL:.2e}, x' {eX:.2e}, displacement {edX:.2e}, oracle retries {retries}, "
+          f"|LL^T - K/n| / max {eB:.2e}", flush=True)
     assert flags == 0 and retries == 0
     assert eL <= 1e-5 and eX <= 1e-6 and edX <= 1e-3
+    assert eB <= 1e-13   # Cholesky's backward error is of order n unit roundoffs at most
     assert np.array_equal(L, np.tril(L)) and np.all(np.diag(L) > 0)
     c._ws.pop(f"chol{n}", None)
 
