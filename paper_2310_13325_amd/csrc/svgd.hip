@@ -1051,9 +1051,23 @@ __global__ __launch_bounds__(1024) void chol_retry_kernel(const float *D, const 
 // copy transposed (LfT[j][i] = L[i][j], the layout the noise product stages).
 // Each element of A is read and rewritten by the thread that writes its
 // transposed copy.
-__global__ void chol_output_kernel(double *A, float *LfT, int n, const uint32_t *state) {
+// With L16 set (the BF16 noise product) it writes instead the row-major BF16
+// pair of L: L16[i n + j] = hi = bf16(L[i][j]), L16[n^2 + i n + j] =
+// bf16(L[i][j] - hi), each thread on one element in row-major order.
+__global__ void chol_output_kernel(double *A, float *LfT, uint16_t *L16, int n,
+                                   const uint32_t *state) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)n * n) return;
+  const long long nn = (long long)n * n;
+  if (e >= nn) return;
+  if (L16) {
+    const int i = int(e / n), j = int(e - (e / n) * n);   // e = i n + j
+    const double v = (j <= i && !state[1]) ? A[e] : 0.0;
+    A[e] = v;
+    const uint16_t h = f32_to_bf16_rne(float(v));
+    L16[e] = h;
+    L16[nn + e] = f32_to_bf16_rne(float(v - double(bf16_to_f32(h))));
+    return;
+  }
   const int j = int(e / n), i = int(e - (e / n) * n);   // e = j n + i
   double *a = A + (long long)i * n + j;
   const double v = (j <= i && !state[1]) ? *a : 0.0;
@@ -1244,6 +1258,58 @@ __global__ __launch_bounds__(UT) void update_mfma_kernel(const float *K, const f
   if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
 }
 
+// Noise epilogue shared by the noise kernels: x <- clip(x + scale sqrt(vq) acc)
+// for the block's 256 x 128 results (wave (wi, wj) holds rows wi 64 .., columns
+// wj 64 .. as 2 x 2 tiles of 32 x 32 in the matrix-core result layout), in
+// batches of four result registers, loads before stores.
+__device__ __forceinline__ void noise_epilogue(const f32x16_t (&acc)[2][2], int i0, long long a0,
+                                               int wi, int wj, int lane, const float *vq,
+                                               float *x, const float *lo, const float *hi, int n,
+                                               long long d, float scale, uint32_t *status) {
+  const int lrow = wi * 64 + 4 * (lane >> 5);
+  const int lcol = wj * 64 + (lane & 31);
+  const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
+  float sc[2], lov[2], hiv[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const long long a = a0 + lcol + q * 32;
+    sc[q] = (vq && a < d) ? scale * sqrtf(vq[a]) : scale;
+    lov[q] = (lo && a < d) ? lo[a] : 0.0f;
+    hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
+  }
+  bool bad = false;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int rb = 0; rb < 16; rb += 4) {
+      float xv[4][2];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
+        const int i = i0 + lrow + lr;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const bool in = i < n && a0 + lcol + q * 32 < d;
+          xv[rr][q] = x[in ? el + (long long)lr * d + q * 32 : 0];
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
+        if (i0 + lrow + lr >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (a0 + lcol + q * 32 >= d) continue;
+          float v = fmaf(sc[q], acc[m][q][r], xv[rr][q]);
+          if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
+          bad |= !isfinite(v);
+          x[el + (long long)lr * d + q * 32] = v;
+        }
+      }
+    }
+  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+}
+
 // The sSVGD noise on the FP32 matrix cores, after the update has added eps phi
 // (without the clip): x <- clip(x + sqrt(2 eps) sqrt(vq) (L Xi)) per element,
 // vq = 1 / q of the diagonal matrix kernel (or 1).  Same blocks, staging and
@@ -1316,49 +1382,150 @@ __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const 
           acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m], fb[q], acc[m][q], 0, 0, 0);
     }
   }
-  // epilogue in batches of four result registers, loads before stores
-  const int lrow = wi * 64 + 4 * (lane >> 5);
-  const int lcol = wj * 64 + (lane & 31);
-  const long long el = (long long)(i0 + lrow) * d + a0 + lcol;
-  float sc[2], lov[2], hiv[2];
+  noise_epilogue(acc, i0, a0, wi, wj, lane, vq, x, lo, hi, n, d, scale, status);
+}
+
+// The same noise on the BF16 matrix cores, for the BF16 path beyond one
+// workgroup's Cholesky: L and Xi are each split into a BF16 pair (v = hi + lo,
+// hi = bf16(v), lo = bf16(v - hi)) and L Xi ~ Lh Xh + Lh Xl + Ll Xh, three
+// products with FP32 accumulation (the dropped Ll Xl and the rounding of the
+// pairs leave about 2^-16 relative per term).  L comes as its row-major BF16
+// pair (Lh[i][j], then Ll), written by the Cholesky's output kernel; Xi is
+// FP32 and split while it is staged.  Blocks, their order (longest first) and
+// the epilogue are those of noise_mfma_kernel.  Per stage of NK = 32 steps of
+// j the A rows are copied as 16-byte chunks into rows of NAP ushorts (16-byte
+// fragment reads at a pitch of 20 dwords hit every bank once per 16 lanes);
+// B is kept as Bs[k][a], and a lane gathers the 8 values of its fragment from
+// 8 rows (the pitch NBP puts lanes 32..63 eight rows down on the other banks).
+constexpr int NK = 32, NAP = NK + 8, NBP = UN + 8;
+__global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, const float *xi,
+                                                          const float *vq, float *x,
+                                                          const float *lo, const float *hi, int n,
+                                                          long long d, int mblocks, int vec,
+                                                          float scale, uint32_t *status) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[UM][NAP], Al[UM][NAP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[NK][NBP], Bl[NK][NBP];
+  const long long nc = (d + UN - 1) / UN;
+  const int xcd = int(blockIdx.x) & 7, kb = int(blockIdx.x) >> 3;
+  const long long cb0 = xcd * nc / 8;
+  const int ncx = int((xcd + 1) * nc / 8 - cb0);
+  if (kb >= mblocks * ncx) return;
+  const int i0 = (mblocks - 1 - kb / ncx) * UM;
+  const long long a0 = (cb0 + kb % ncx) * UN;
+  const int jend = min(n, i0 + UM);
+  const long long nn = (long long)n * n;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  // staging: A chunk c = t + UT it (it < 4) is part c / 1024 (0: hi, 1: lo),
+  // row (c % 1024) / 4, 8 values from j0 + 8 (c % 4); B float4 c = t + UT it
+  // (it < 2) is row c / 32, columns 4 (c % 32) .. + 3
+  uint4 pa[4];
+  float4 pb[2];
+  auto load_stage = [&](int j0) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const long long a = a0 + lcol + q * 32;
-    sc[q] = (vq && a < d) ? scale * sqrtf(vq[a]) : scale;
-    lov[q] = (lo && a < d) ? lo[a] : 0.0f;
-    hiv[q] = (lo && a < d) ? hi[a] : 0.0f;
-  }
-  bool bad = false;
+    for (int it = 0; it < 4; ++it) {
+      const int c = t + UT * it, part = c >> 10, row = (c & 1023) >> 2, j = j0 + 8 * (c & 3);
+      const int i = i0 + row;
+      const uint16_t *src = L16 + part * nn + (long long)i * n + j;
+      if (vec && i < n && j + 7 < n) {
+        pa[it] = *reinterpret_cast<const uint4 *>(src);
+      } else {
+        uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (i < n && j + e < n) v[e >> 1] |= uint32_t(src[e]) << (16 * (e & 1));
+        pa[it] = make_uint4(v[0], v[1], v[2], v[3]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int c = t + UT * it, k = c >> 5, col = 4 * (c & 31);
+      const int j = j0 + k;
+      const long long a = a0 + col;
+      const float *src = xi + (long long)j * d + a;
+      if (vec && j < n && a + 3 < d) {
+        pb[it] = *reinterpret_cast<const float4 *>(src);
+      } else {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (j < n && a + e < d) ? src[e] : 0.0f;
+        pb[it] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int c = t + UT * it, part = c >> 10, row = (c & 1023) >> 2, ch = c & 3;
+      uint16_t *dst = part ? &Al[row][8 * ch] : &Ah[row][8 * ch];
+      *reinterpret_cast<uint4 *>(dst) = pa[it];
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int c = t + UT * it, k = c >> 5, col = 4 * (c & 31);
+      const float v[4] = {pb[it].x, pb[it].y, pb[it].z, pb[it].w};
+      uint32_t h[2] = {0u, 0u}, l[2] = {0u, 0u};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t hb = f32_to_bf16_rne(v[e]);
+        const uint16_t lb = f32_to_bf16_rne(v[e] - bf16_to_f32(hb));
+        h[e >> 1] |= uint32_t(hb) << (16 * (e & 1));
+        l[e >> 1] |= uint32_t(lb) << (16 * (e & 1));
+      }
+      *reinterpret_cast<uint2 *>(&Bh[k][col]) = make_uint2(h[0], h[1]);
+      *reinterpret_cast<uint2 *>(&Bl[k][col]) = make_uint2(l[0], l[1]);
+    }
+  };
+  auto bfrag = [&](const uint16_t (*B)[NBP], int k, int col) {
+    uint32_t v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = uint32_t(B[k + 2 * e][col]) | (uint32_t(B[k + 2 * e + 1][col]) << 16);
+    bf16x8_t f;
+    __builtin_memcpy(&f, v, 16);
+    return f;
+  };
+  f32x16_t acc[2][2];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int rb = 0; rb < 16; rb += 4) {
-      float xv[4][2];
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
-        const int i = i0 + lrow + lr;
+      for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
+  load_stage(0);
+  for (int j0 = 0; j0 < jend; j0 += NK) {
+    __syncthreads();
+    store_stage();
+    __syncthreads();
+    if (j0 + NK < jend) load_stage(j0 + NK);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const bool in = i < n && a0 + lcol + q * 32 < d;
-          xv[rr][q] = x[in ? el + (long long)lr * d + q * 32 : 0];
-        }
+    for (int ks = 0; ks < NK; ks += 16) {
+      const int kq = ks + 8 * (lane >> 5);
+      bf16x8_t fah[2], fal[2], fbh[2], fbl[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int row = wi * 64 + m * 32 + (lane & 31);
+        const uint4 rh = *reinterpret_cast<const uint4 *>(&Ah[row][kq]);
+        const uint4 rl = *reinterpret_cast<const uint4 *>(&Al[row][kq]);
+        __builtin_memcpy(&fah[m], &rh, 16);
+        __builtin_memcpy(&fal[m], &rl, 16);
       }
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int r = rb + rr, lr = m * 32 + 8 * (r >> 2) + (r & 3);
-        if (i0 + lrow + lr >= n) continue;
+      for (int q = 0; q < 2; ++q) {
+        const int col = wj * 64 + q * 32 + (lane & 31);
+        fbh[q] = bfrag(Bh, kq, col);
+        fbl[q] = bfrag(Bl, kq, col);
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          if (a0 + lcol + q * 32 >= d) continue;
-          float v = fmaf(sc[q], acc[m][q][r], xv[rr][q]);
-          if (lo) v = fminf(fmaxf(v, lov[q]), hiv[q]);
-          bad |= !isfinite(v);
-          x[el + (long long)lr * d + q * 32] = v;
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[m], fbh[q], acc[m][q], 0, 0, 0);
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbl[q], acc[m][q], 0, 0, 0);
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbh[q], acc[m][q], 0, 0, 0);
         }
-      }
     }
-  if (bad) atomicOr(status, VIP_FLAG_NONFINITE);
+  }
+  noise_epilogue(acc, i0, a0, wi, wj, lane, vq, x, lo, hi, n, d, scale, status);
 }
 
 // The same update with the product K B on the BF16 matrix cores: K rounded to
@@ -1991,6 +2158,10 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
   }
   VIP_LAUNCH_CHECK();
   if (noise) {
+    // BF16 path beyond one workgroup's Cholesky: the noise product on the BF16
+    // matrix cores, L as a BF16 pair in the space of its FP32 copy (4 n^2 bytes)
+    const bool noise16 = g16 && n > kCholMax;
+    uint16_t *L16 = noise16 ? reinterpret_cast<uint16_t *>(P.Lf) : nullptr;
     if (n <= kCholMax) {
       cholesky_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, P.Lf, n, 6, P.status);
       VIP_LAUNCH_CHECK();
@@ -2012,7 +2183,7 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       }
       chol_retry_kernel<<<dim3(1), dim3(1024), 0, s>>>(P.D, P.h2, P.L, n, 6, P.chol, P.status);
       VIP_LAUNCH_CHECK();
-      chol_output_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.L, P.Lf, n, P.chol);
+      chol_output_kernel<<<dim3(nn_blocks), dim3(256), 0, s>>>(P.L, P.Lf, L16, n, P.chol);
       VIP_LAUNCH_CHECK();
     }
     const float *xin = xi;
@@ -2024,12 +2195,20 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
       VIP_LAUNCH_CHECK();
       xin = P.xi;
     }
-    const int nvec = (d % 4 == 0) && (n % 4 == 0) &&
-                     (reinterpret_cast<uintptr_t>(xin) % 16 == 0) &&
-                     (reinterpret_cast<uintptr_t>(P.Lf) % 16 == 0);
     const long long nxcd = (((d + UN - 1) / UN) + 7) / 8;   // column blocks per XCD, at most
-    noise_mfma_kernel<<<dim3(unsigned(8 * mblocks * nxcd)), dim3(UT), 0, s>>>(
-        P.Lf, xin, vq, x, lo, hi, n, d, mblocks, nvec, float(std::sqrt(2.0 * eps)), P.status);
+    if (noise16) {
+      const int v16 = (d % 4 == 0) && (n % 8 == 0) &&
+                      (reinterpret_cast<uintptr_t>(xin) % 16 == 0) &&
+                      (reinterpret_cast<uintptr_t>(L16) % 16 == 0);
+      noise_bf16x3_kernel<<<dim3(unsigned(8 * mblocks * nxcd)), dim3(UT), 0, s>>>(
+          L16, xin, vq, x, lo, hi, n, d, mblocks, v16, float(std::sqrt(2.0 * eps)), P.status);
+    } else {
+      const int nvec = (d % 4 == 0) && (n % 4 == 0) &&
+                       (reinterpret_cast<uintptr_t>(xin) % 16 == 0) &&
+                       (reinterpret_cast<uintptr_t>(P.Lf) % 16 == 0);
+      noise_mfma_kernel<<<dim3(unsigned(8 * mblocks * nxcd)), dim3(UT), 0, s>>>(
+          P.Lf, xin, vq, x, lo, hi, n, d, mblocks, nvec, float(std::sqrt(2.0 * eps)), P.status);
+    }
   }
   VIP_LAUNCH_CHECK();
   return VIP_OK;

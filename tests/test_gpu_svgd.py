@@ -396,11 +396,40 @@ def test_ssvgd_blocked_cholesky_coincident_particles(n, ndup):
     c._ws.pop("chol_dup", None)
 
 
+@pytest.mark.parametrize("n, d", [(200, 1024), (201, 1001), (600, 4096)])
+def test_ssvgd_bf16_noise_product_matches_fp64(n, d):
+    """The BF16 path's noise product beyond one workgroup's Cholesky (L and Xi
+    each split into a BF16 pair, three products on the BF16 matrix cores).
+    With the particles near 0, x' keeps the noise to FP32 precision, and
+    x' - x - eps phi (the library's own phi) matches sqrt(2 eps) L Xi, formed in
+    FP64 from the library's own L and the same normals, to 1e-4 relative L2.
+    Odd n and d take the element-wise staging."""
+    eps = 0.5
+    rng = np.random.default_rng(90 + n)
+    X = (0.1 * rng.standard_normal((n, d))).astype(np.float32).astype(np.float64)
+    G = rng.standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    xi = rng.standard_normal((n, d)).astype(np.float32).astype(np.float64)
+    c = ctx()
+    x = dev(X)
+    print(f"BF16 noise product n={n} d={d}", flush=True)
+    ws = vb.vip_ssvgd_step(c, x, dev(G), eps, xi=dev(xi), gram_prec=vb.VIP_GRAM_BF16,
+                           ws_tag=f"noise16_{n}")
+    flags = c.poll(ws)
+    D, K, h2, phi, L = _inspect(ws, n, d)
+    eta = x.cpu().numpy().astype(np.float64) - X - eps * phi.astype(np.float64)
+    eta_ref = np.sqrt(2.0 * eps) * (L @ xi)
+    e = rel(eta, eta_ref)
+    print(f"  noise vs FP64 L Xi: {e:.2e}", flush=True)
+    assert flags & ~vb.VIP_FLAG_JITTER == 0
+    assert e <= 1e-4
+    c._ws.pop(f"noise16_{n}", None)
+
+
 @pytest.mark.parametrize("n", [600, 2048])
 def test_ssvgd_bf16_path_matches_oracle(n):
     """sSVGD on the BF16 path (BF16 Gram in 256 x 256 blocks, K in BF16 times
-    the split B on the BF16 matrix cores, blocked FP64 Cholesky, noise L Xi on
-    the FP32 matrix cores) with the same normals on both sides, d = 4096: phi
+    the split B on the BF16 matrix cores, blocked FP64 Cholesky, noise L Xi as
+    three BF16 products of split pairs) with the same normals on both sides, d = 4096: phi
     and L to 1e-3 relative L2 (the BF16 path's tolerance), the displacement
     x' - x to 1e-3."""
     from oracle import cref
