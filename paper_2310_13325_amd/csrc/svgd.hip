@@ -1393,18 +1393,19 @@ __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const 
 // pair (Lh[i][j], then Ll), written by the Cholesky's output kernel; Xi is
 // FP32 and split while it is staged.  Blocks, their order (longest first) and
 // the epilogue are those of noise_mfma_kernel.  Per stage of NK = 32 steps of
-// j the A rows are copied as 16-byte chunks into rows of NAP ushorts (16-byte
-// fragment reads at a pitch of 20 dwords hit every bank once per 16 lanes);
-// B is kept as Bs[k][a], and a lane gathers the 8 values of its fragment from
-// 8 rows (the pitch NBP puts lanes 32..63 eight rows down on the other banks).
-constexpr int NK = 32, NAP = NK + 8, NBP = UN + 8;
+// j both operands sit in LDS with k contiguous, in rows of NAP ushorts (16-byte
+// fragment reads at a pitch of 20 dwords hit every bank once per 16 lanes):
+// the A rows are copied as 16-byte chunks, and a thread loads 4 consecutive j
+// of one Xi column (each load one coalesced row segment over the wave), splits
+// them and writes them as one 8-byte run of its column's row.
+constexpr int NK = 32, NAP = NK + 8;
 __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, const float *xi,
                                                           const float *vq, float *x,
                                                           const float *lo, const float *hi, int n,
                                                           long long d, int mblocks, int vec,
                                                           float scale, uint32_t *status) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[UM][NAP], Al[UM][NAP];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[NK][NBP], Bl[NK][NBP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[UN][NAP], Bl[UN][NAP];
   const long long nc = (d + UN - 1) / UN;
   const int xcd = int(blockIdx.x) & 7, kb = int(blockIdx.x) >> 3;
   const long long cb0 = xcd * nc / 8;
@@ -1417,8 +1418,8 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
   // staging: A chunk c = t + UT it (it < 4) is part c / 1024 (0: hi, 1: lo),
-  // row (c % 1024) / 4, 8 values from j0 + 8 (c % 4); B float4 c = t + UT it
-  // (it < 2) is row c / 32, columns 4 (c % 32) .. + 3
+  // row (c % 1024) / 4, 8 values from j0 + 8 (c % 4); B group it (< 2) of
+  // thread t is column t % 128, steps 16 it + 4 (t / 128) .. + 3
   uint4 pa[4];
   float4 pb[2];
   auto load_stage = [&](int j0) {
@@ -1437,20 +1438,14 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
         pa[it] = make_uint4(v[0], v[1], v[2], v[3]);
       }
     }
+    const long long a = a0 + (t & (UN - 1));
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-      const int c = t + UT * it, k = c >> 5, col = 4 * (c & 31);
-      const int j = j0 + k;
-      const long long a = a0 + col;
-      const float *src = xi + (long long)j * d + a;
-      if (vec && j < n && a + 3 < d) {
-        pb[it] = *reinterpret_cast<const float4 *>(src);
-      } else {
-        float v[4];
+      const int jb = j0 + 16 * it + 4 * (t >> 7);
+      float v[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (j < n && a + e < d) ? src[e] : 0.0f;
-        pb[it] = make_float4(v[0], v[1], v[2], v[3]);
-      }
+      for (int e = 0; e < 4; ++e) v[e] = (jb + e < n && a < d) ? xi[(long long)(jb + e) * d + a] : 0.0f;
+      pb[it] = make_float4(v[0], v[1], v[2], v[3]);
     }
   };
   auto store_stage = [&]() {
@@ -1462,7 +1457,7 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
     }
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-      const int c = t + UT * it, k = c >> 5, col = 4 * (c & 31);
+      const int col = t & (UN - 1), k = 16 * it + 4 * (t >> 7);
       const float v[4] = {pb[it].x, pb[it].y, pb[it].z, pb[it].w};
       uint32_t h[2] = {0u, 0u}, l[2] = {0u, 0u};
 #pragma unroll
@@ -1472,17 +1467,9 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
         h[e >> 1] |= uint32_t(hb) << (16 * (e & 1));
         l[e >> 1] |= uint32_t(lb) << (16 * (e & 1));
       }
-      *reinterpret_cast<uint2 *>(&Bh[k][col]) = make_uint2(h[0], h[1]);
-      *reinterpret_cast<uint2 *>(&Bl[k][col]) = make_uint2(l[0], l[1]);
+      *reinterpret_cast<uint2 *>(&Bh[col][k]) = make_uint2(h[0], h[1]);
+      *reinterpret_cast<uint2 *>(&Bl[col][k]) = make_uint2(l[0], l[1]);
     }
-  };
-  auto bfrag = [&](const uint16_t (*B)[NBP], int k, int col) {
-    uint32_t v[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = uint32_t(B[k + 2 * e][col]) | (uint32_t(B[k + 2 * e + 1][col]) << 16);
-    bf16x8_t f;
-    __builtin_memcpy(&f, v, 16);
-    return f;
   };
   f32x16_t acc[2][2];
 #pragma unroll
@@ -1512,17 +1499,28 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int col = wj * 64 + q * 32 + (lane & 31);
-        fbh[q] = bfrag(Bh, kq, col);
-        fbl[q] = bfrag(Bl, kq, col);
+        const uint4 rh = *reinterpret_cast<const uint4 *>(&Bh[col][kq]);
+        const uint4 rl = *reinterpret_cast<const uint4 *>(&Bl[col][kq]);
+        __builtin_memcpy(&fbh[q], &rh, 16);
+        __builtin_memcpy(&fbl[q], &rl, 16);
       }
+      // the three products in turns over the four tiles, so that no product
+      // waits on the one just issued into the same accumulator
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < 2; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[m], fbh[q], acc[m][q], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbl[q], acc[m][q], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
           acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbh[q], acc[m][q], 0, 0, 0);
-        }
     }
   }
   noise_epilogue(acc, i0, a0, wi, wj, lane, vq, x, lo, hi, n, d, scale, status);
