@@ -429,8 +429,10 @@ vip_status vip_svgd_step_ex(vip_ctx *ctx, int32_t n, int64_t d, float *x, const 
  * that needs jitter (numerically coincident particles) reruns in one
  * workgroup with the matrix in global memory: correct, but slow for large n
  * (VIP_FLAG_JITTER reports it).  The direction phi is formed as in
- * vip_svgd_step (with the same Gram precision); the noise product L xi runs on
- * the FP32 matrix cores over the lower triangle of L, and the clip follows it.
+ * vip_svgd_step (with the same Gram precision); the noise product L xi runs
+ * over the lower triangle of L on the FP32 matrix cores, or, with the BF16
+ * Gram and n > 128, as three BF16 matrix-core products of L and xi each split
+ * into a BF16 pair (hi + lo; about 2^-16 relative), and the clip follows it.
  * xi: device float [n][d] standard normals, or NULL to draw them with
  * Philox4x32-10 (key = seed, counter = (element/4, stream)) and Box-Muller. */
 vip_status vip_ssvgd_step(vip_ctx *ctx, int32_t n, int64_t d, float *x, const float *g, double eps,
