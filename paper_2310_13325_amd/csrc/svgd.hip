@@ -576,18 +576,20 @@ __device__ __forceinline__ void wave_count(uint32_t *h, bool act, uint32_t digit
   if (act && !same) atomicAdd(&h[digit], 1u);
 }
 
-// One pass of the radix select: histogram of the digit at `shift` over the
-// keys (float bits of D >= 0) that match each target's prefix so far.  While
-// the two targets still share their prefix, one histogram serves both.
+// One pass of the radix select: histogram of the `bits`-wide digit at `shift`
+// over the keys (float bits of D >= 0) that match each target's prefix so far
+// (three passes of 11, 11 and 10 bits).  While the two targets still share
+// their prefix, one histogram serves both.
 // Sixteen keys per thread and trip, as four 16-byte loads (when D is
 // aligned) issued before any of them is counted; the loop runs the same
 // number of times on every lane.
-constexpr int RADIX_V = 4;   // 4-key groups per thread and trip
+constexpr int RADIX_V = 4;       // 4-key groups per thread and trip
+constexpr int RADIX_BINS = 2048;  // bins of the widest digit
 __global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, int offdiag,
-                                                         int vec, int shift, const uint32_t *sel,
-                                                         uint32_t *hist) {
-  __shared__ uint32_t h[2][256];
-  for (int b = threadIdx.x; b < 512; b += 256) (&h[0][0])[b] = 0;
+                                                         int vec, int shift, int bits,
+                                                         const uint32_t *sel, uint32_t *hist) {
+  __shared__ uint32_t h[2][RADIX_BINS];
+  for (int b = threadIdx.x; b < 2 * RADIX_BINS; b += 256) (&h[0][0])[b] = 0;
   __syncthreads();
   const uint32_t p0 = sel[0], m0 = sel[1], p1 = sel[3], m1 = sel[4];
   const bool one = p0 == p1 && m0 == m1;
@@ -618,30 +620,38 @@ __global__ __launch_bounds__(256) void radix_hist_kernel(const float *D, int n, 
           in = i < j;
         }
         const uint32_t key = __float_as_uint(v[u][q]);
-        const uint32_t digit = (key >> shift) & 0xFFu;
+        const uint32_t digit = (key >> shift) & ((1u << bits) - 1u);
         wave_count(h[0], in && (key & m0) == p0, digit);
         if (!one) wave_count(h[1], in && (key & m1) == p1, digit);
       }
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < 512; b += 256) {
-    const uint32_t v = one ? h[0][b & 255] : (&h[0][0])[b];
+  const int nb = 1 << bits;
+  for (int b = threadIdx.x; b < 2 * RADIX_BINS; b += 256) {
+    const int bb = b & (RADIX_BINS - 1);
+    if (bb >= nb) continue;
+    const uint32_t v = one ? h[0][bb] : (&h[0][0])[b];
     if (v) atomicAdd(&hist[b], v);
   }
 }
 
-// One wave per target: each lane holds 4 bins, a wave prefix sum finds the
-// lane whose bins contain the rank, that lane resolves the bin; the
-// histogram is then cleared for the next pass.
+// One wave per target: each lane holds RADIX_BINS / 64 consecutive bins, a
+// wave prefix sum of the lanes' totals finds the lane whose bins contain the
+// rank, that lane resolves the bin; the histogram is then cleared for the
+// next pass.
 __global__ __launch_bounds__(128) void radix_select_kernel(uint32_t *sel, uint32_t *hist,
-                                                           int shift) {
+                                                           int shift, int bits) {
+  constexpr int PL = RADIX_BINS / 64;
   const int t = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint32_t *s = sel + 3 * t;
-  uint32_t *h = hist + 256 * t;
+  uint32_t *h = hist + RADIX_BINS * t + PL * lane;
   const uint32_t k = s[2];
-  const uint32_t b0 = h[4 * lane], b1 = h[4 * lane + 1], b2 = h[4 * lane + 2], b3 = h[4 * lane + 3];
-  uint32_t incl = b0 + b1 + b2 + b3;
+  uint32_t bins[PL];
+  uint32_t own = 0;
+#pragma unroll
+  for (int e = 0; e < PL; ++e) own += (bins[e] = h[e]);
+  uint32_t incl = own;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t v = __shfl_up(incl, off, 64);
     if (lane >= off) incl += v;
@@ -649,20 +659,19 @@ __global__ __launch_bounds__(128) void radix_select_kernel(uint32_t *sel, uint32
   const unsigned long long hit = __ballot(incl > k);
   const int first = hit ? __ffsll(hit) - 1 : 63;
   if (lane == first) {
-    const uint32_t excl = incl - (b0 + b1 + b2 + b3);
-    uint32_t r = k - excl, b = 4 * lane;
-    const uint32_t bins[4] = {b0, b1, b2, b3};
+    uint32_t r = k - (incl - own);
     int e = 0;
-    for (; e < 3; ++e) {
+    for (; e < PL - 1; ++e) {
       if (r < bins[e]) break;
       r -= bins[e];
     }
-    b += e;
+    const uint32_t b = uint32_t(PL * lane + e);
     s[0] |= b << shift;
-    s[1] |= 0xFFu << shift;
+    s[1] |= ((1u << bits) - 1u) << shift;
     s[2] = r;
   }
-  h[4 * lane] = h[4 * lane + 1] = h[4 * lane + 2] = h[4 * lane + 3] = 0;
+#pragma unroll
+  for (int e = 0; e < PL; ++e) h[e] = 0;
 }
 
 __global__ void bandwidth_kernel(const uint32_t *sel, long long count, int n, int mode,
@@ -2099,12 +2108,15 @@ static vip_status svgd_common(vip_ctx *ctx, int32_t n, int64_t d, float *x, cons
     if (count > 0) {
       unsigned hb = unsigned(std::min<long long>((nn + 4095) / 4096, 1024));
       const int vec = reinterpret_cast<uintptr_t>(P.D) % 16 == 0;
-      VIP_TRY(fill_u32(s, P.hist, 512, 0u));   // each select clears it for the next pass
-      for (int shift = 24; shift >= 0; shift -= 8) {
+      // each select clears it for the next pass
+      VIP_TRY(fill_u32(s, P.hist, 2 * RADIX_BINS, 0u));
+      constexpr int kShift[3] = {21, 10, 0}, kBits[3] = {11, 11, 10};   // 32 bits in 3 digits
+      for (int ps = 0; ps < 3; ++ps) {
         radix_hist_kernel<<<dim3(hb), dim3(256), 0, s>>>(P.D, n, bw_mode == VIP_BW_MEDIAN_OFFDIAG,
-                                                         vec, shift, P.sel, P.hist);
+                                                         vec, kShift[ps], kBits[ps], P.sel,
+                                                         P.hist);
         VIP_LAUNCH_CHECK();
-        radix_select_kernel<<<dim3(1), dim3(128), 0, s>>>(P.sel, P.hist, shift);
+        radix_select_kernel<<<dim3(1), dim3(128), 0, s>>>(P.sel, P.hist, kShift[ps], kBits[ps]);
         VIP_LAUNCH_CHECK();
       }
     }

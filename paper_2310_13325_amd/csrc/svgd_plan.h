@@ -91,7 +91,7 @@ inline void plan_svgd(int n, long long d, char *base, SvgdPlan *P) {
   P->D = A.take<float>(nn);
   P->K = A.take<float>(nn);
   P->s = A.take<float>(size_t(n));
-  P->hist = A.take<uint32_t>(512);
+  P->hist = A.take<uint32_t>(2 * 2048);   // two radix histograms of up to 2048 bins
   P->sel = A.take<uint32_t>(8);
   P->chol = A.take<uint32_t>(2);
   P->h2 = A.take<double>(1);
