@@ -1408,7 +1408,7 @@ __global__ __launch_bounds__(UT) void noise_mfma_kernel(const float *LfT, const 
 // of one Xi column (each load one coalesced row segment over the wave), splits
 // them and writes them as one 8-byte run of its column's row.
 constexpr int NK = 32, NAP = NK + 8;
-__global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, const float *xi,
+__global__ __launch_bounds__(UT) __attribute__((amdgpu_waves_per_eu(4, 4))) void noise_bf16x3_kernel(const uint16_t *L16, const float *xi,
                                                           const float *vq, float *x,
                                                           const float *lo, const float *hi, int n,
                                                           long long d, int mblocks, int vec,
@@ -1431,7 +1431,7 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
   // thread t is column t % 128, steps 16 it + 4 (t / 128) .. + 3
   uint4 pa[4];
   float4 pb[2];
-  auto load_stage = [&](int j0) {
+  auto load_a = [&](int j0) {
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int c = t + UT * it, part = c >> 10, row = (c & 1023) >> 2, j = j0 + 8 * (c & 3);
@@ -1447,6 +1447,8 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
         pa[it] = make_uint4(v[0], v[1], v[2], v[3]);
       }
     }
+  };
+  auto load_b = [&](int j0) {
     const long long a = a0 + (t & (UN - 1));
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -1457,13 +1459,15 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
       pb[it] = make_float4(v[0], v[1], v[2], v[3]);
     }
   };
-  auto store_stage = [&]() {
+  auto store_a = [&]() {
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int c = t + UT * it, part = c >> 10, row = (c & 1023) >> 2, ch = c & 3;
       uint16_t *dst = part ? &Al[row][8 * ch] : &Ah[row][8 * ch];
       *reinterpret_cast<uint4 *>(dst) = pa[it];
     }
+  };
+  auto store_b = [&]() {
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       const int col = t & (UN - 1), k = 16 * it + 4 * (t >> 7);
@@ -1487,49 +1491,59 @@ __global__ __launch_bounds__(UT) void noise_bf16x3_kernel(const uint16_t *L16, c
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[m][q][r] = 0.0f;
-  load_stage(0);
   for (int j0 = 0; j0 < jend; j0 += NK) {
+    // no prefetch into registers: two blocks share a compute unit, and one
+    // block's staging overlaps the other's products
+    load_a(j0);
     __syncthreads();
-    store_stage();
+    store_a();
+    load_b(j0);
+    store_b();
     __syncthreads();
-    if (j0 + NK < jend) load_stage(j0 + NK);
 #pragma unroll
     for (int ks = 0; ks < NK; ks += 16) {
       const int kq = ks + 8 * (lane >> 5);
-      bf16x8_t fah[2], fal[2], fbh[2], fbl[2];
+      // fragments as the products need them (24 registers live, not 32): the
+      // three products in turns over the four tiles, so that no product waits
+      // on the one just issued into the same accumulator
+      bf16x8_t fa[2], fbh[2], fbl[2];
+      auto afrag = [&](const uint16_t (*A)[NAP], int m) {
+        const uint4 r = *reinterpret_cast<const uint4 *>(&A[wi * 64 + m * 32 + (lane & 31)][kq]);
+        bf16x8_t f;
+        __builtin_memcpy(&f, &r, 16);
+        return f;
+      };
+      auto bfrag = [&](const uint16_t (*B)[NAP], int q) {
+        const uint4 r = *reinterpret_cast<const uint4 *>(&B[wj * 64 + q * 32 + (lane & 31)][kq]);
+        bf16x8_t f;
+        __builtin_memcpy(&f, &r, 16);
+        return f;
+      };
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int row = wi * 64 + m * 32 + (lane & 31);
-        const uint4 rh = *reinterpret_cast<const uint4 *>(&Ah[row][kq]);
-        const uint4 rl = *reinterpret_cast<const uint4 *>(&Al[row][kq]);
-        __builtin_memcpy(&fah[m], &rh, 16);
-        __builtin_memcpy(&fal[m], &rl, 16);
+      for (int e = 0; e < 2; ++e) {
+        fa[e] = afrag(Al, e);
+        fbh[e] = bfrag(Bh, e);
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int col = wj * 64 + q * 32 + (lane & 31);
-        const uint4 rh = *reinterpret_cast<const uint4 *>(&Bh[col][kq]);
-        const uint4 rl = *reinterpret_cast<const uint4 *>(&Bl[col][kq]);
-        __builtin_memcpy(&fbh[q], &rh, 16);
-        __builtin_memcpy(&fbl[q], &rl, 16);
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fbh[q], acc[m][q], 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        fa[e] = afrag(Ah, e);
+        fbl[e] = bfrag(Bl, e);
       }
-      // the three products in turns over the four tiles, so that no product
-      // waits on the one just issued into the same accumulator
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[m], fbh[q], acc[m][q], 0, 0, 0);
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fbl[q], acc[m][q], 0, 0, 0);
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbl[q], acc[m][q], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[m], fbh[q], acc[m][q], 0, 0, 0);
+          acc[m][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[m], fbh[q], acc[m][q], 0, 0, 0);
     }
   }
   noise_epilogue(acc, i0, a0, wi, wj, lane, vq, x, lo, hi, n, d, scale, status);
