@@ -526,8 +526,10 @@ __global__ __launch_bounds__(256) void gram_dist_kernel(const float *part, float
   if (t < 2 * DT) {
     const int k = (t < DT ? i0 : j0) + t % DT;
     float g = 0.0f;
-    if (k < n)
+    if (k < n) {
+#pragma unroll 8
       for (int p = 0; p < splits; ++p) g += part[p * nn + (long long)k * n + k];
+    }
     dg[t / DT][t % DT] = g;
   }
   __syncthreads();
@@ -539,6 +541,9 @@ __global__ __launch_bounds__(256) void gram_dist_kernel(const float *part, float
     float v = 0.0f;
     if (i < n && j < n) {
       float g = 0.0f;
+      // unrolled so that the partials' loads are in flight together (the sum
+      // keeps its order)
+#pragma unroll 8
       for (int p = 0; p < splits; ++p) g += part[p * nn + (long long)i * n + j];
       v = (i == j) ? 0.0f : fmaxf(dg[0][r] + dg[1][c] - 2.0f * g, 0.0f);
       bad |= !isfinite(v);
